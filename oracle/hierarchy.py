@@ -1,0 +1,424 @@
+"""Oracle: setup of the fully coupled aggregation AMG hierarchy (FP64, CPU).
+
+Test infrastructure only (see the package docstring).
+
+Paper passages followed:
+* fully coupled multigrid with segregated transfers P = blkdiag(P^u, P^l)
+  and R = P^T (Sec. 4.1, segregated transfer operators);
+* displacement aggregation on K with slave/master interface couplings
+  dropped on the fly (Sec. 4.2);
+* multiplier aggregates as images of the slave displacement aggregates
+  (Sec. 4.3, Alg. 1);
+* tentative (non-smoothed) transfers from aggregates plus null space
+  (Sec. 3.1.2);
+* Galerkin coarse blocks and the merged direct solve on the coarsest level
+  (weak-scaling study, solver settings);
+* SIMPLEC lumping of |K| and the Schur approximation (Sec. 5.1.3, SIMPLE
+  variants).
+
+Readings where the paper is silent (all listed in the design notes):
+* Dirichlet dof = row of K whose only stored entry is its diagonal and whose
+  G row is empty;
+* standard aggregation = three-phase greedy aggregation in natural order
+  (phase 1: root + all neighbours when none is taken; phase 2 on a snapshot:
+  join the neighbouring aggregate holding most neighbours, ties to the
+  smallest id; phase 3: leftovers seed new aggregates with their free
+  neighbours);
+* "D_ij != 0" in Alg. 1 = a stored entry of G's slave rows; sparsity
+  patterns of coarse blocks are symbolic (no numerical dropping);
+* coarse slave / master interface nodes = aggregates containing such nodes;
+* tentative prolongator by per-aggregate modified Gram-Schmidt QR of the
+  null-space rows (Dirichlet rows zeroed), columns in order, R_ii > 0;
+* multiplier null space = one constant per Cartesian component.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclass
+class AMGOptions:
+    max_levels: int = 4
+    max_coarse_rows: int = 1000
+    nu_pre: int = 2
+    nu_post: int = 2
+    jacobi_sweeps: int = 1
+    jacobi_omega: float = 0.8
+    simple_alpha: float = 0.8
+    atilde: str = "rowsum_abs"  # or "diag"
+    jacobi_diag: str = "atilde"  # relaxation diagonal of the prediction: "atilde" or "diag"
+
+
+@dataclass
+class Level:
+    K: sp.csr_matrix
+    G: sp.csr_matrix
+    B: sp.csr_matrix
+    C: sp.csr_matrix
+    bs_u: int
+    bs_l: int
+    slave_nodes: np.ndarray  # bool per displacement node
+    master_nodes: np.ndarray
+    lm_node: np.ndarray  # multiplier dof -> pseudo-node
+    nullspace_u: np.ndarray
+    nullspace_l: np.ndarray
+    dirichlet: np.ndarray = None
+    agg_u: np.ndarray = None  # node -> aggregate (this level's nodes), -1 = none
+    agg_l: np.ndarray = None  # multiplier pseudo-node -> multiplier aggregate
+    dmap: np.ndarray = None  # displacement aggregate -> multiplier aggregate (-1 none)
+    P_u: sp.csr_matrix = None
+    P_l: sp.csr_matrix = None
+    dinv: np.ndarray = None
+    atilde_inv: np.ndarray = None
+    sd_inv: np.ndarray = None
+    A_inv: np.ndarray = None  # coarsest level only
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_u(self):
+        return self.K.shape[0]
+
+    @property
+    def n_l(self):
+        return self.C.shape[0]
+
+    @property
+    def n(self):
+        return self.n_u + self.n_l
+
+    def A(self) -> sp.csr_matrix:
+        return sp.bmat([[self.K, self.G], [self.B, self.C]], format="csr")
+
+    def nnz(self) -> int:
+        return self.K.nnz + self.G.nnz + self.B.nnz + self.C.nnz
+
+
+# ----------------------------------------------------------------------------
+# graph and aggregation
+
+
+def dirichlet_dofs(K: sp.csr_matrix, G: sp.csr_matrix) -> np.ndarray:
+    """Rows of K holding only their diagonal entry, with an empty G row."""
+    n = K.shape[0]
+    cnt = np.diff(K.indptr)
+    first = np.where(cnt > 0, K.indices[np.minimum(K.indptr[:-1], max(K.nnz - 1, 0))], -1)
+    diag_only = (cnt == 1) & (first == np.arange(n))
+    g_empty = np.diff(G.indptr) == 0
+    return diag_only & g_empty
+
+
+def node_graph(K, bs, dirichlet, slave_nodes, master_nodes):
+    """Node adjacency (CSR arrays, sorted, no self loops).
+
+    Nodes i != j are adjacent when a stored entry of K's (i, j) block lies in
+    a non-Dirichlet row and a non-Dirichlet column.  Pairs of a slave
+    interface node and a master interface node are dropped (Sec. 4.2).
+    """
+    n_nodes = K.shape[0] // bs
+    coo = K.tocoo()
+    keep = ~dirichlet[coo.row] & ~dirichlet[coo.col]
+    r = coo.row[keep] // bs
+    c = coo.col[keep] // bs
+    keep = r != c
+    keep &= ~((slave_nodes[r] & master_nodes[c]) | (master_nodes[r] & slave_nodes[c]))
+    Gn = sp.csr_matrix((np.ones(int(keep.sum())), (r[keep], c[keep])), shape=(n_nodes, n_nodes))
+    Gn.sum_duplicates()
+    Gn.sort_indices()
+    return Gn.indptr.astype(np.int64), Gn.indices.astype(np.int64)
+
+
+def aggregate(indptr, indices, active):
+    """Three-phase greedy aggregation in natural node order.
+
+    Only active nodes take part; edges to inactive nodes are ignored.
+    Returns (agg, n_agg): agg[i] = aggregate id, -1 for inactive nodes.
+    """
+    n = len(active)
+    agg = np.full(n, -1, dtype=np.int64)
+    n_agg = 0
+
+    def nbrs(i):
+        nb = indices[indptr[i]:indptr[i + 1]]
+        return nb[active[nb]]
+
+    # phase 1: a node whose neighbourhood is untouched becomes a root and
+    # takes all of its neighbours
+    for i in range(n):
+        if not active[i] or agg[i] >= 0:
+            continue
+        nb = nbrs(i)
+        if nb.size and (agg[nb] >= 0).any():
+            continue
+        agg[i] = n_agg
+        agg[nb] = n_agg
+        n_agg += 1
+    # phase 2: leftovers join the adjacent phase-1 aggregate holding most of
+    # their neighbours (ties: smallest aggregate id), decided on a snapshot
+    snap = agg.copy()
+    for i in range(n):
+        if not active[i] or snap[i] >= 0:
+            continue
+        a = snap[nbrs(i)]
+        a = a[a >= 0]
+        if a.size == 0:
+            continue
+        ids, counts = np.unique(a, return_counts=True)  # ids ascending
+        agg[i] = ids[np.argmax(counts)]  # argmax takes the first (smallest id) maximum
+    # phase 3: remaining nodes seed new aggregates with their free neighbours
+    for i in range(n):
+        if not active[i] or agg[i] >= 0:
+            continue
+        nb = nbrs(i)
+        agg[i] = n_agg
+        agg[nb[agg[nb] < 0]] = n_agg
+        n_agg += 1
+    return agg, n_agg
+
+
+def lagmult_aggregation(disp_agg, n_disp_agg, slave_dofs, Gmat, bs_u, lm_node, n_lm_nodes):
+    """Alg. 1 (Sec. 4.3): multiplier aggregates from displacement aggregates.
+
+    Walks the slave displacement dofs i in ascending order; k is the
+    aggregate of i's node; every multiplier j coupled to i (a stored entry
+    G[i, j], i.e. D_ij != 0 with D^T held in G's slave rows) puts j's
+    pseudo-node into the multiplier aggregate d(k), created on first
+    encounter.  A pseudo-node keeps its first assignment.
+    Returns (lm_agg per pseudo-node, dmap per displacement aggregate, count).
+    """
+    lm_agg = np.full(n_lm_nodes, -1, dtype=np.int64)
+    dmap = np.full(n_disp_agg, -1, dtype=np.int64)
+    n_l = 0
+    for i in slave_dofs:
+        k = disp_agg[i // bs_u]
+        if k < 0:
+            continue
+        for j in Gmat.indices[Gmat.indptr[i]:Gmat.indptr[i + 1]]:
+            if dmap[k] < 0:
+                dmap[k] = n_l
+                n_l += 1
+            nl = lm_node[j]
+            if lm_agg[nl] < 0:
+                lm_agg[nl] = dmap[k]
+    return lm_agg, dmap, n_l
+
+
+def tentative_prolongator(agg, n_agg, node_of_dof, nullspace, zero_rows, rank_tol=1e-12):
+    """Tentative prolongator of aggregation AMG (Sec. 3.1.2).
+
+    For each aggregate the null-space rows of its dofs (rows in zero_rows
+    set to zero) are factored by modified Gram-Schmidt, column by column:
+    Q becomes the aggregate's block of P, R the coarse null-space rows.
+    The pattern of P holds all n_ns coarse columns for every fine dof of an
+    aggregated node that is not a zeroed row (explicit zeros kept).
+    Returns (P csr, coarse nullspace).
+    """
+    n_rows, n_ns = nullspace.shape
+    dof_agg = np.where(node_of_dof >= 0, agg[np.maximum(node_of_dof, 0)], -1)
+    dof_agg = np.where(zero_rows, -1, dof_agg)
+    order = np.argsort(dof_agg, kind="stable")
+    order = order[dof_agg[order] >= 0]
+    starts = np.searchsorted(dof_agg[order], np.arange(n_agg + 1))
+    Pvals = np.zeros((n_rows, n_ns))
+    coarse = np.zeros((n_agg * n_ns, n_ns))
+    for a in range(n_agg):
+        rows = order[starts[a]:starts[a + 1]]  # ascending dof order
+        Bm = nullspace[rows, :].copy()
+        Q = np.zeros_like(Bm)
+        R = np.zeros((n_ns, n_ns))
+        for k in range(n_ns):
+            v = Bm[:, k].copy()
+            for i in range(k):
+                R[i, k] = np.dot(Q[:, i], v)
+                v = v - R[i, k] * Q[:, i]
+            nv = np.sqrt(np.dot(v, v))
+            if not nv > rank_tol * np.sqrt(np.dot(Bm[:, k], Bm[:, k])):
+                raise np.linalg.LinAlgError(f"rank-deficient aggregate {a}")
+            R[k, k] = nv
+            Q[:, k] = v / nv
+        Pvals[rows, :] = Q
+        coarse[a * n_ns:(a + 1) * n_ns, :] = R
+    has = dof_agg >= 0
+    rows_idx = np.repeat(np.nonzero(has)[0], n_ns)
+    cols_idx = (dof_agg[has][:, None] * n_ns + np.arange(n_ns)[None, :]).ravel()
+    vals = Pvals[has].ravel()
+    indptr = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(np.where(has, n_ns, 0), out=indptr[1:])
+    P = sp.csr_matrix((vals, cols_idx, indptr), shape=(n_rows, n_agg * n_ns))
+    return P, coarse
+
+
+def _pattern(M):
+    S = sp.csr_matrix((np.ones(M.nnz), M.indices.copy(), M.indptr.copy()), shape=M.shape)
+    return S
+
+
+def galerkin(R, A, P):
+    """R A P on the symbolic pattern of the product (no numerical dropping)."""
+    S = (_pattern(R) @ _pattern(A) @ _pattern(P)).tocsr()
+    S.sort_indices()
+    N = (R @ A @ P).tocsr()
+    N.sort_indices()
+    out = sp.csr_matrix((np.zeros(S.nnz), S.indices.copy(), S.indptr.copy()), shape=S.shape)
+    if N.nnz:
+        nrow = np.repeat(np.arange(N.shape[0]), np.diff(N.indptr))
+        key_s = np.repeat(np.arange(S.shape[0]), np.diff(S.indptr)).astype(np.int64) * S.shape[1] + S.indices
+        key_n = nrow.astype(np.int64) * S.shape[1] + N.indices
+        pos = np.searchsorted(key_s, key_n)
+        assert np.all(key_s[pos] == key_n)
+        out.data[pos] = N.data
+    return out
+
+
+# ----------------------------------------------------------------------------
+# smoother data and coarsest level
+
+
+def smoother_data(L: Level, opts: AMGOptions):
+    """The SIMPLEC lumping Atilde = diag(sum_j |K_ij|) (or diag K), the
+    diagonal of the Schur approximation B Atilde^-1 G - C (Sec. 5.1.3, SIMPLE
+    variants; written with the stored C = -Z), and the relaxation diagonal of
+    the Jacobi prediction.
+
+    Reading: the paper's cheap prediction is a few sweeps of a convergent
+    relaxation (SGS in its runs, Sec. 5.2).  Plain damped Jacobi on diag(K)
+    with the damping 0.8 diverges on 3D hex8 elasticity (the spectrum of
+    diag(K)^-1 K reaches about 3.15), so the default relaxation diagonal is
+    the same lumped Atilde, which bounds the spectrum of Atilde^-1 K by one
+    for symmetric positive semi-definite K (Gershgorin) and keeps the damped
+    sweep convergent.  "diag" selects plain diag(K)."""
+    dK = L.K.diagonal()
+    if np.any(dK == 0.0):
+        raise ZeroDivisionError("zero diagonal in K")
+    if opts.atilde == "rowsum_abs":
+        At = np.asarray(abs(L.K).sum(axis=1)).ravel()
+    else:
+        At = dK.copy()
+    if np.any(At == 0.0):
+        raise ZeroDivisionError("zero Atilde")
+    At_inv = 1.0 / At
+    # diag(B Atilde^-1 G)_j = sum_i B[j, i] G[i, j] / Atilde_i
+    BG = L.B.multiply(L.G.T.tocsr()).tocsr()
+    Sd = np.asarray(BG @ At_inv).ravel() - L.C.diagonal()
+    if np.any(Sd == 0.0):
+        raise ZeroDivisionError("zero Schur diagonal")
+    L.dinv = At_inv.copy() if opts.jacobi_diag == "atilde" else 1.0 / dK
+    L.atilde_inv = At_inv
+    L.sd_inv = 1.0 / Sd
+
+
+class SingularCoarse(np.linalg.LinAlgError):
+    pass
+
+
+def coarse_inverse(L: Level, pivot_tol=1e-13):
+    """Merged dense coarsest matrix, LU with partial pivoting (LAPACK) and
+    its inverse.  A pivot below pivot_tol times the largest entry of A_c
+    marks the coarsest matrix singular."""
+    import scipy.linalg as sla
+
+    Ad = L.A().toarray()
+    lu, piv = sla.lu_factor(Ad, check_finite=True)
+    if np.min(np.abs(np.diag(lu))) <= pivot_tol * np.max(np.abs(Ad)):
+        raise SingularCoarse("singular coarsest matrix")
+    L.A_inv = sla.lu_solve((lu, piv), np.eye(Ad.shape[0]))
+
+
+# ----------------------------------------------------------------------------
+# hierarchy
+
+
+def _level_from_problem(prob) -> Level:
+    d = prob.dim
+    n_nodes = prob.n_u // d
+    slave_nodes = np.zeros(n_nodes, dtype=bool)
+    master_nodes = np.zeros(n_nodes, dtype=bool)
+    slave_nodes[np.asarray(prob.slave_dofs) // d] = True
+    master_nodes[np.asarray(prob.master_dofs) // d] = True
+    n_l = prob.n_lam
+    Zl = np.zeros((n_l, d))
+    Zl[np.arange(n_l), np.arange(n_l) % d] = 1.0
+    return Level(
+        K=sp.csr_matrix(prob.K),
+        G=sp.csr_matrix(prob.G),
+        B=sp.csr_matrix(prob.B),
+        C=sp.csr_matrix(prob.C),
+        bs_u=d,
+        bs_l=d,
+        slave_nodes=slave_nodes,
+        master_nodes=master_nodes,
+        lm_node=np.asarray(prob.lm_node, dtype=np.int64),
+        nullspace_u=np.asarray(prob.nullspace, dtype=float),
+        nullspace_l=Zl,
+    )
+
+
+def coarsen(L: Level):
+    """Aggregate level L and return the next coarser level."""
+    dirichlet = dirichlet_dofs(L.K, L.G)
+    L.dirichlet = dirichlet
+    n_nodes = L.n_u // L.bs_u
+    node_dirichlet_all = dirichlet.reshape(n_nodes, L.bs_u).all(axis=1)
+    active = ~node_dirichlet_all
+    indptr, indices = node_graph(L.K, L.bs_u, dirichlet, L.slave_nodes, L.master_nodes)
+    agg_u, n_agg_u = aggregate(indptr, indices, active)
+
+    slave_dofs = np.nonzero(np.repeat(L.slave_nodes, L.bs_u))[0]
+    n_lm_nodes = int(L.lm_node.max()) + 1 if L.n_l else 0
+    agg_l, dmap, n_agg_l = lagmult_aggregation(agg_u, n_agg_u, slave_dofs, L.G, L.bs_u, L.lm_node, n_lm_nodes)
+    if np.any(agg_l < 0):
+        raise ValueError("multiplier pseudo-node without a slave coupling")
+
+    node_of_dof_u = np.arange(L.n_u) // L.bs_u
+    P_u, ns_u_c = tentative_prolongator(agg_u, n_agg_u, node_of_dof_u, L.nullspace_u, dirichlet)
+    P_l, ns_l_c = tentative_prolongator(agg_l, n_agg_l, L.lm_node, L.nullspace_l, np.zeros(L.n_l, bool))
+    R_u = P_u.T.tocsr()
+    R_l = P_l.T.tocsr()
+    L.agg_u, L.agg_l, L.dmap, L.P_u, L.P_l = agg_u, agg_l, dmap, P_u, P_l
+
+    n_ns_u = L.nullspace_u.shape[1]
+    n_ns_l = L.nullspace_l.shape[1]
+    slave_c = np.zeros(n_agg_u, dtype=bool)
+    master_c = np.zeros(n_agg_u, dtype=bool)
+    sel = agg_u >= 0
+    slave_c[agg_u[sel & L.slave_nodes]] = True
+    master_c[agg_u[sel & L.master_nodes]] = True
+    return Level(
+        K=galerkin(R_u, L.K, P_u),
+        G=galerkin(R_u, L.G, P_l),
+        B=galerkin(R_l, L.B, P_u),
+        C=galerkin(R_l, L.C, P_l),
+        bs_u=n_ns_u,
+        bs_l=n_ns_l,
+        slave_nodes=slave_c,
+        master_nodes=master_c,
+        lm_node=np.arange(n_agg_l * n_ns_l) // n_ns_l,
+        nullspace_u=ns_u_c,
+        nullspace_l=ns_l_c,
+    )
+
+
+def build_hierarchy(prob, opts: AMGOptions = None, factor_coarsest: bool = True):
+    """Levels 0..L-1; the last one carries the dense coarsest inverse.
+
+    Coarsening continues while fewer than max_levels exist and the current
+    coarsest level has more than max_coarse_rows rows.
+    """
+    opts = opts or AMGOptions()
+    levels = [_level_from_problem(prob)]
+    while len(levels) < opts.max_levels and levels[-1].n > opts.max_coarse_rows:
+        nxt = coarsen(levels[-1])
+        if nxt.n >= levels[-1].n:
+            break
+        levels.append(nxt)
+    for L in levels[:-1]:
+        smoother_data(L, opts)
+    if factor_coarsest:
+        coarse_inverse(levels[-1])
+    return levels
+
+
+def operator_complexity(levels) -> float:
+    return sum(L.nnz() for L in levels) / levels[0].nnz()

@@ -1,0 +1,215 @@
+"""Pins for the seeded input generator (CPU).
+
+The generator is input-side, but its properties are checked against what the
+paper and the mathematics fix: printed dof counts, rigid-body invariance of
+the stiffness, patch test, dual-mortar identities.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from contactgen import make_contact_problem, make_workload, weak_scaling_problem
+from contactgen.fe import box_element_coords, element_stiffness_split, lame_from_E_nu
+from contactgen.mortar import mortar_1d, mortar_face
+from contactgen.problem import _assemble_body, _element_shapes, _grid_coords
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_rows(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([int(v) for v in line.split()])
+    return rows
+
+
+def test_table3_first_row_from_generator():
+    kappa, n_u, n_l, n = _read_rows("weak_scaling_table3_sizes.txt")[0]
+    p = weak_scaling_problem(kappa)
+    assert (p.n_u, p.n_lam, p.n) == (n_u, n_l, n)
+
+
+@pytest.mark.parametrize("kappa", [1, 2, 3])
+def test_table3_counting_small(kappa):
+    # node counting of the generator vs the structure of the table: two blocks of
+    # (2k+1)^2 (k+1) nodes, 3 dofs each; slave face (2k+1)^2 nodes, 3 multipliers each
+    p = weak_scaling_problem(kappa)
+    assert p.n_u == 2 * 3 * (2 * kappa + 1) ** 2 * (kappa + 1)
+    assert p.n_lam == 3 * (2 * kappa + 1) ** 2
+
+
+def test_table3_all_rows_consistent():
+    # every printed row obeys the generator's node counting
+    for kappa, n_u, n_l, n in _read_rows("weak_scaling_table3_sizes.txt"):
+        assert n_u == 6 * (2 * kappa + 1) ** 2 * (kappa + 1)
+        assert n_l == 3 * (2 * kappa + 1) ** 2
+        assert n == n_u + n_l
+
+
+def test_two_bodies_worked_example_counts():
+    (n_u, n_l), = _read_rows("two_bodies_dofs.txt")
+    p = make_contact_problem(3, (9, 9, 9), (9, 9, 9))
+    assert (p.n_u, p.n_lam) == (n_u, n_l)
+
+
+def test_workload_sizes():
+    p = make_workload("contact2d_16")
+    assert (p.n_u, p.n_lam) == (1190, 34)
+    p = make_workload("contact3d_6")
+    assert (p.n_u, p.n_lam) == (2373, 147)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_element_zero_energy_modes(dim):
+    Kl, Km = element_stiffness_split(box_element_coords([0.3, 0.5, 0.7][:dim]))
+    lam, mu = lame_from_E_nu(1.0, 0.3)
+    ev = np.linalg.eigvalsh(lam * Kl + mu * Km)
+    n_rbm = 3 if dim == 2 else 6
+    assert np.sum(np.abs(ev) < 1e-10 * ev.max()) == n_rbm
+    assert ev.min() > -1e-10 * ev.max()
+
+
+def _body(dim, nel, sigma=0.0):
+    axes = _grid_coords(nel, [0.0] * dim, [1.0, 0.8, 0.6][:dim])
+    Kl, Km = _element_shapes(nel, axes, None)
+    rng = np.random.default_rng(1)
+    grid = tuple(reversed(nel))
+    E = rng.lognormal(0.0, sigma, grid) if sigma else np.ones(grid)
+    lam, mu = lame_from_E_nu(E, 0.3)
+    K = _assemble_body(nel, axes, lam, mu, Kl, Km)
+    mesh = np.meshgrid(*axes, indexing="ij")
+    X = np.stack([m.transpose(tuple(reversed(range(dim)))).ravel() for m in mesh], axis=1)
+    return K, X
+
+
+@pytest.mark.parametrize("dim,nel", [(2, (4, 3)), (3, (3, 2, 2))])
+def test_body_stiffness_symmetric_and_rigid_modes(dim, nel):
+    K, X = _body(dim, nel, sigma=1.0)
+    assert abs(K - K.T).max() < 1e-14 * abs(K).max()
+    n = X.shape[0]
+    modes = []
+    for c in range(dim):
+        t = np.zeros((n, dim))
+        t[:, c] = 1.0
+        modes.append(t.ravel())
+    if dim == 2:
+        modes.append(np.stack([-X[:, 1], X[:, 0]], axis=1).ravel())
+    else:
+        x, y, z = X.T
+        modes.append(np.stack([0 * x, -z, y], axis=1).ravel())
+        modes.append(np.stack([z, 0 * x, -x], axis=1).ravel())
+        modes.append(np.stack([-y, x, 0 * x], axis=1).ravel())
+    for m in modes:
+        assert np.abs(K @ m).max() < 1e-12 * abs(K).max()
+
+
+@pytest.mark.parametrize("dim,nel", [(2, (4, 4)), (3, (3, 3, 3))])
+def test_patch_test_interior_balance(dim, nel):
+    # a linear displacement field has constant stress: nodal forces vanish at interior nodes
+    K, X = _body(dim, nel)
+    rng = np.random.default_rng(0)
+    F = rng.standard_normal((dim, dim))
+    u = (X @ F.T).ravel()
+    f = (K @ u).reshape(-1, dim)
+    hi = np.array([1.0, 0.8, 0.6][:dim])
+    interior = np.all((X > 1e-12) & (X < hi - 1e-12), axis=1)
+    assert interior.any()
+    assert np.abs(f[interior]).max() < 1e-12 * np.abs(f).max()
+
+
+def test_mortar_1d_identities():
+    xs = np.linspace(0.0, 1.0, 9)
+    xm = np.linspace(0.0, 1.0, 12)
+    D, M = mortar_1d(xs, xm)
+    h = xs[1] - xs[0]
+    # D_jj = int N_j: h in the interior, h/2 at the ends
+    assert np.allclose(D[1:-1], h, rtol=0, atol=1e-15)
+    assert np.allclose(D[[0, -1]], h / 2, rtol=0, atol=1e-15)
+    # master partition of unity: rows of M sum to D_jj
+    assert np.allclose(M.sum(axis=1), D, rtol=0, atol=1e-14)
+    # matching meshes: M = D
+    D2, M2 = mortar_1d(xs, xs)
+    assert np.allclose(M2, np.diag(D2), rtol=0, atol=1e-15)
+
+
+def test_mortar_1d_brute_force_quadrature():
+    xs = np.linspace(0.0, 1.0, 6)
+    xm = np.array([0.0, 0.13, 0.4, 0.41, 0.77, 1.0])
+    D, M = mortar_1d(xs, xm)
+    # midpoint rule with many points on psi_j N_k
+    x = (np.arange(200000) + 0.5) / 200000
+    def hat(nodes, k, x):
+        return np.interp(x, nodes, np.eye(len(nodes))[k])
+    es = np.clip(np.searchsorted(xs, x, side="right") - 1, 0, len(xs) - 2)
+    t = (x - xs[es]) / (xs[es + 1] - xs[es])
+    for j in range(len(xs)):
+        psi = np.zeros_like(x)
+        left = es == j      # j is the first node of its element
+        psi[left] = 2 * (1 - t[left]) - t[left]
+        right = es == j - 1  # j is the second node
+        psi[right] = 2 * t[right] - (1 - t[right])
+        for k in range(len(xm)):
+            ref = np.mean(psi * hat(xm, k, x))
+            assert abs(ref - M[j, k]) < 1e-8
+        assert abs(np.mean(psi * hat(xs, j, x)) - D[j]) < 1e-8
+        # biorthogonality against the other slave shape functions
+        for k in range(len(xs)):
+            if k != j:
+                assert abs(np.mean(psi * hat(xs, k, x))) < 1e-8
+
+
+def test_mortar_face_is_kronecker():
+    ax_s = [np.linspace(0, 1, 4), np.linspace(0, 1, 5)]
+    ax_m = [np.linspace(0, 1, 6), np.linspace(0, 1, 3)]
+    D, M = mortar_face(ax_s, ax_m)
+    Dx, Mx = mortar_1d(ax_s[0], ax_m[0])
+    Dy, My = mortar_1d(ax_s[1], ax_m[1])
+    # face node index = ix + nx * iy
+    for iy in range(5):
+        for ix in range(4):
+            j = ix + 4 * iy
+            assert abs(D[j] - Dx[ix] * Dy[iy]) < 1e-15
+            for ky in range(3):
+                for kx in range(6):
+                    assert abs(M[j, kx + 6 * ky] - Mx[ix, kx] * My[iy, ky]) < 1e-15
+
+
+def test_blocks_structure_flat():
+    p = make_workload("contact3d_6")
+    d = p.dim
+    # slave interface rows of G carry D on the matching multiplier, master rows -M^T
+    G = p.G.tocsr()
+    sl = p.slave_dofs
+    for i in sl[:30]:
+        cols = G.indices[G.indptr[i]:G.indptr[i + 1]]
+        assert len(cols) == 1 and cols[0] % d == i % d
+    # normal constraint rows equal the matching rows of G^T; tangential rows of B empty
+    GT = G.T.tocsr()
+    B = p.B.tocsr()
+    for j in range(p.n_lam):
+        if j % d == d - 1:
+            assert abs(B[j] - GT[j]).max() < 1e-15
+        else:
+            assert B[j].nnz == 0
+            assert p.C[j, j] == 1.0
+    # Dirichlet rows are identity rows with zero columns
+    K = p.K.tocsr()
+    for i in np.nonzero(p.dirichlet)[0][:50]:
+        assert K[i].nnz == 1 and K[i, i] == 1.0
+        assert K[:, i].nnz == 1
+
+
+def test_curved_interface_small():
+    p = make_contact_problem(3, (4, 4, 4), (5, 5, 4), curve_amp=0.05, E_sigma=2.0, nu=(0.25, 0.35), seed=3)
+    K = p.K
+    assert abs(K - K.T).max() < 1e-13 * abs(K).max()
+    # master partition of unity still holds with the surface weight
+    Dd = np.array([p.G[i, j] for i, j in zip(p.slave_dofs[::3], range(0, p.n_lam, 3))])
+    assert np.all(Dd > 0)
+    A = p.full_matrix().tocsc()
+    x = sp.linalg.spsolve(A, p.b)
+    assert np.linalg.norm(A @ x - p.b) < 1e-10 * np.linalg.norm(p.b)
