@@ -1,0 +1,212 @@
+/*
+ * camg.h -- C-ABI of libcamg: fully coupled block-AMG preconditioned FGMRES
+ * for mortar-contact saddle-point systems on one AMD Instinct MI355X (gfx950).
+ *
+ * The system is the compact block form of the linearised mortar-contact
+ * problem (Wiesner, Mayr, Popp, Gee, Wall, "Algebraic multigrid methods for
+ * saddle point systems arising from mortar contact formulations",
+ * Sec. 2.3, the 2x2 block system and its short notation):
+ *
+ *     [ K  G ] [u]   [f]       G = C1^T  (n_u x n_l, upper-right coupling)
+ *     [ B  C ] [l] = [g]       B = C2    (n_l x n_u, constraint rows)
+ *                              C = -Z    (n_l x n_l)
+ *
+ * Vectors crossing this interface are contiguous [u; l] of length
+ * n = n_u + n_l.
+ *
+ * Conventions for every entry point:
+ *  - Return value: CAMG_OK (0) on success, CAMG_NOT_CONVERGED (1) when a
+ *    solve stopped at its iteration limit (the output then holds the last
+ *    iterate), or a negative CAMG_ERR_* code.  amg_last_error() returns a
+ *    message for the most recent failure on the calling thread.
+ *  - "host" pointers point to CPU memory, "device" pointers to memory on the
+ *    GPU that is current when amg_setup is called (e.g. torch CUDA tensors
+ *    on ROCm).  The library never frees caller memory.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued on it; entry points that return numbers computed on the GPU
+ *    synchronise that stream before returning.
+ *  - A handle may be used from one thread at a time; calls on one handle
+ *    that overlap on different streams race.
+ */
+#ifndef CAMG_H
+#define CAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CAMG_OK 0
+#define CAMG_NOT_CONVERGED 1
+#define CAMG_ERR_INVALID_ARG (-1)      /* NULL / out-of-range argument         */
+#define CAMG_ERR_SHAPE (-2)            /* block sizes or CSR structure invalid */
+#define CAMG_ERR_NONFINITE (-3)        /* NaN/Inf in input or residual         */
+#define CAMG_ERR_ZERO_DIAG (-4)        /* zero Jacobi / Atilde / Schur diagonal*/
+#define CAMG_ERR_RANK_DEFICIENT_AGG (-5) /* null space rank-deficient on an aggregate */
+#define CAMG_ERR_SINGULAR_COARSE (-6)  /* coarsest merged matrix singular      */
+#define CAMG_ERR_HIP (-7)              /* HIP runtime error                    */
+#define CAMG_ERR_OOM (-8)              /* device or host allocation failed     */
+#define CAMG_ERR_UNMAPPED_MULTIPLIER (-9) /* multiplier coupled to no slave dof */
+
+typedef struct amg_handle amg_handle;
+
+/* Compressed sparse row matrix, host pointers.  rowptr has nrows+1 entries
+ * starting at 0; column indices are sorted and unique within each row;
+ * nnz = rowptr[nrows] must be below 2^31.  An all-empty block (nnz = 0) may
+ * pass NULL col/val. */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+} amg_csr;
+
+/* Problem statement, host pointers (Sec. 2.3 blocks; Sec. 4.2/4.3 interface
+ * data).  Layout rules:
+ *  - displacement dofs are node-major: dof = node * dim + component;
+ *  - slave_dofs / master_dofs list the displacement dofs of the slave /
+ *    master interface nodes (any order); a node is an interface node when
+ *    one of its dofs is listed;
+ *  - lm_node maps each multiplier dof to its pseudo-node (NULL: j / dim);
+ *    the component of multiplier j is j % dim;
+ *  - nullspace is n_u x n_ns, column-major (rigid-body modes for
+ *    elasticity); NULL means the dim translations.
+ * All data are copied; the caller may free them after amg_setup returns. */
+typedef struct {
+  int32_t dim;                 /* 2 or 3: dofs per displacement node      */
+  amg_csr K, G, B, C;          /* n_u x n_u, n_u x n_l, n_l x n_u, n_l x n_l */
+  int32_t n_slave, n_master;
+  const int32_t* slave_dofs;
+  const int32_t* master_dofs;
+  const int32_t* lm_node;      /* optional, length n_l                    */
+  int32_t n_ns;
+  const double* nullspace;     /* optional, n_u * n_ns                    */
+} amg_problem;
+
+/* Preconditioner options (defaults from amg_default_options). */
+#define CAMG_ATILDE_ROWSUM_ABS 0 /* SIMPLEC lumping diag(sum_j |K_ij|)     */
+#define CAMG_ATILDE_DIAG 1       /* diag(K)                                 */
+#define CAMG_JACOBI_ATILDE 0     /* Jacobi prediction relaxes with Atilde   */
+#define CAMG_JACOBI_DIAG 1       /* Jacobi prediction relaxes with diag(K)  */
+#define CAMG_PREC_FP64 0         /* hierarchy, smoother, transfers in FP64  */
+#define CAMG_PREC_MIXED 1        /* ... in FP32 inside the FP64 FGMRES      */
+typedef struct {
+  int32_t max_levels;      /* >= 1; 1 = direct solve of the whole system  */
+  int32_t max_coarse_rows; /* stop coarsening at or below this many rows   */
+  int32_t nu_pre, nu_post; /* CheapSIMPLE sweeps before / after correction */
+  int32_t jacobi_sweeps;   /* damped Jacobi sweeps in the prediction (>=1) */
+  int32_t atilde;          /* CAMG_ATILDE_*                                */
+  int32_t jacobi_diag;     /* CAMG_JACOBI_*                                */
+  int32_t precision;       /* CAMG_PREC_*                                  */
+  double jacobi_omega;     /* Jacobi damping                               */
+  double simple_alpha;     /* SIMPLE damping (Alg. 3)                      */
+} amg_options;
+
+/* FGMRES options. */
+typedef struct {
+  int32_t m;           /* restart length (Krylov vectors per cycle), 1..512 */
+  int32_t max_iters;   /* total iteration limit                            */
+  int32_t fixed_iters; /* > 0: run exactly this many iterations, ignore rtol */
+  int32_t check_every; /* read the residual estimate every k iterations (>=1) */
+  double rtol;         /* stop when ||b - A x|| <= rtol ||b - A x0||        */
+} amg_gmres_options;
+
+typedef struct {
+  int32_t iters, restarts, status;
+  double rel_res_est;  /* |g_{j+1}| / ||r0|| from the Hessenberg recursion   */
+  double rel_res_true; /* ||b - A x|| / ||r0||, recomputed at the end        */
+  double seconds;      /* device time of the solve (hipEvents)               */
+} amg_gmres_result;
+
+typedef struct {
+  int64_t n_u, n_l;
+  int64_t nnz_K, nnz_G, nnz_B, nnz_C;
+  int32_t bs_u, bs_l;     /* dofs per displacement node / multiplier node */
+  int64_t n_nodes_u, n_nodes_l;
+  int64_t n_agg_u, n_agg_l; /* aggregates built on this level (0 on the coarsest) */
+  double op_complexity;   /* sum over levels of nnz / level-0 nnz (all blocks) */
+} amg_level_info;
+
+void amg_default_options(amg_options* opts);
+void amg_default_gmres_options(amg_gmres_options* opts);
+
+/* Builds the hierarchy (Sec. 4: displacement aggregation with slave/master
+ * couplings dropped, multiplier aggregation by Alg. 1, tentative segregated
+ * transfers, Galerkin blocks; Sec. 5.1.3 smoother data; dense LU of the
+ * merged coarsest matrix) and uploads it to the current device.
+ * On success *out owns all device memory of the hierarchy. */
+int amg_setup(const amg_problem* prob, const amg_options* opts, void* hip_stream, amg_handle** out);
+
+/* The same hierarchy construction on the host only, with no device upload
+ * and no HIP call: the handle answers amg_num_levels, amg_level_info_get,
+ * amg_get_aggregates and amg_get_level_matrix; device entry points return
+ * CAMG_ERR_INVALID_ARG for it.  Release with amg_destroy. */
+int amg_setup_host(const amg_problem* prob, const amg_options* opts, amg_handle** out);
+
+int amg_num_levels(const amg_handle* h);
+int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out);
+
+/* Aggregates of `level` (0 <= level < levels-1), host arrays:
+ * disp_agg[n_nodes_u] (node -> aggregate, -1 for clamped nodes),
+ * lm_agg[n_nodes_l] (multiplier pseudo-node -> aggregate of Alg. 1).
+ * Either pointer may be NULL. */
+int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_t* lm_agg);
+
+/* Copies block `which` (0=K, 1=G, 2=B, 3=C, 4=P_u, 5=P_l) of `level` to host
+ * arrays in FP64 (rowptr: nrows+1, col/val: nnz).  Call with NULL arrays to
+ * query *nrows, *ncols, *nnz first. */
+int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols,
+                         int64_t* nnz, int64_t* rowptr, int32_t* col, double* val);
+
+/* Replaces the values of the level-0 blocks (device pointers, FP64, same
+ * patterns and order as at setup; NULL keeps a block).  The outer FGMRES
+ * operator and the FP64 level-0 smoother operator use the new values; the
+ * coarse levels, the smoother diagonals and an FP32 level-0 copy keep the
+ * setup-time values (a fixed preconditioner for the new operator). */
+int amg_update_fine_values(amg_handle* h, const double* K_val, const double* G_val, const double* B_val,
+                           const double* C_val, void* hip_stream);
+
+/* y = A x (transpose = 0) or y = A^T x on the level-0 operator; device
+ * FP64 vectors of length n.  Asynchronous. */
+int amg_apply_operator(amg_handle* h, int transpose, const double* x, double* y, void* hip_stream);
+
+/* One V-cycle (Sec. 3.1.1, Fig. 2a, started from zero) as preconditioner:
+ * z = M^-1 r (transpose = 0) or z = M^-T r, the exact transpose of the
+ * forward cycle (adjoint sweeps, pre/post counts swapped, A_c^-T).  Device
+ * FP64 vectors of length n; r and z must not overlap.  Asynchronous. */
+int amg_vcycle_apply(amg_handle* h, int transpose, const double* r, double* z, void* hip_stream);
+
+/* Right-preconditioned flexible GMRES(m) with CGS2 and Givens rotations,
+ * one V-cycle per iteration (Sec. 3), on A (transpose = 0) or A^T.
+ * b: device FP64 length n; x: device FP64 length n, initial guess on entry,
+ * solution on exit.  Synchronises hip_stream.  res may be NULL. */
+int fgmres_solve(amg_handle* h, int transpose, const double* b, double* x, const amg_gmres_options* gopts,
+                 amg_gmres_result* res, void* hip_stream);
+
+/* dK[k] = -lam_u[i] * x_u[j] for the k-th stored entry (i, j) of K in setup
+ * order: the gradient of a scalar loss with respect to K's nonzeros, given
+ * the forward solution x and the adjoint solution lam (device FP64, length
+ * n).  dK: device FP64, nnz(K).  Asynchronous. */
+int amg_grad_K(amg_handle* h, const double* lam, const double* x, double* dK, void* hip_stream);
+
+/* Per-kernel timing with hipEvents around every launch of the selected
+ * kernel classes (bit mask of CAMG_KCLASS_*), recorded on the stream the
+ * kernel runs on.  amg_profile_read synchronises and returns the number of
+ * timed launches and their summed duration in milliseconds. */
+#define CAMG_KCLASS_SMOOTH_U 1   /* level-0 residual + Jacobi prediction (CSR) */
+#define CAMG_KCLASS_OPERATOR 2   /* FP64 outer operator apply              */
+#define CAMG_KCLASS_ORTHO 4      /* CGS2 GEMV passes                        */
+#define CAMG_KCLASS_RESIDUAL 8   /* level-0 residual before restriction    */
+int amg_profile_enable(amg_handle* h, int mask);
+int amg_profile_read(amg_handle* h, int kclass, int64_t* launches, double* total_ms);
+
+void amg_destroy(amg_handle* h);
+const char* amg_strerror(int code);
+const char* amg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAMG_H */

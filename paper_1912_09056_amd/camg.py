@@ -1,0 +1,380 @@
+"""ctypes binding of libcamg (the C-ABI declared in include/camg.h).
+
+Argument marshalling only: every step of the solve runs inside the HIP
+library.  Function names match the C entry points; `AMGSolver` bundles a
+handle with torch-allocated device vectors for convenience.
+
+PyTorch supplies device memory and streams.  torch is imported before the
+library is loaded so that both share one HIP runtime in the process.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, byref, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcamg.so")
+
+CAMG_OK = 0
+CAMG_NOT_CONVERGED = 1
+PREC_FP64 = 0
+PREC_MIXED = 1
+KCLASS_SMOOTH_U = 1
+KCLASS_OPERATOR = 2
+KCLASS_ORTHO = 4
+KCLASS_RESIDUAL = 8
+
+
+class amg_csr(Structure):
+    _fields_ = [
+        ("nrows", c_int64),
+        ("ncols", c_int64),
+        ("nnz", c_int64),
+        ("rowptr", POINTER(c_int64)),
+        ("col", POINTER(c_int32)),
+        ("val", POINTER(c_double)),
+    ]
+
+
+class amg_problem(Structure):
+    _fields_ = [
+        ("dim", c_int32),
+        ("K", amg_csr),
+        ("G", amg_csr),
+        ("B", amg_csr),
+        ("C", amg_csr),
+        ("n_slave", c_int32),
+        ("n_master", c_int32),
+        ("slave_dofs", POINTER(c_int32)),
+        ("master_dofs", POINTER(c_int32)),
+        ("lm_node", POINTER(c_int32)),
+        ("n_ns", c_int32),
+        ("nullspace", POINTER(c_double)),
+    ]
+
+
+class amg_options(Structure):
+    _fields_ = [
+        ("max_levels", c_int32),
+        ("max_coarse_rows", c_int32),
+        ("nu_pre", c_int32),
+        ("nu_post", c_int32),
+        ("jacobi_sweeps", c_int32),
+        ("atilde", c_int32),
+        ("jacobi_diag", c_int32),
+        ("precision", c_int32),
+        ("jacobi_omega", c_double),
+        ("simple_alpha", c_double),
+    ]
+
+
+class amg_gmres_options(Structure):
+    _fields_ = [
+        ("m", c_int32),
+        ("max_iters", c_int32),
+        ("fixed_iters", c_int32),
+        ("check_every", c_int32),
+        ("rtol", c_double),
+    ]
+
+
+class amg_gmres_result(Structure):
+    _fields_ = [
+        ("iters", c_int32),
+        ("restarts", c_int32),
+        ("status", c_int32),
+        ("rel_res_est", c_double),
+        ("rel_res_true", c_double),
+        ("seconds", c_double),
+    ]
+
+
+class amg_level_info(Structure):
+    _fields_ = [
+        ("n_u", c_int64),
+        ("n_l", c_int64),
+        ("nnz_K", c_int64),
+        ("nnz_G", c_int64),
+        ("nnz_B", c_int64),
+        ("nnz_C", c_int64),
+        ("bs_u", c_int32),
+        ("bs_l", c_int32),
+        ("n_nodes_u", c_int64),
+        ("n_nodes_l", c_int64),
+        ("n_agg_u", c_int64),
+        ("n_agg_l", c_int64),
+        ("op_complexity", c_double),
+    ]
+
+
+# name -> (restype, argtypes); every symbol declared in include/camg.h
+SIGNATURES = {
+    "amg_default_options": (None, [POINTER(amg_options)]),
+    "amg_default_gmres_options": (None, [POINTER(amg_gmres_options)]),
+    "amg_setup": (c_int, [POINTER(amg_problem), POINTER(amg_options), c_void_p, POINTER(c_void_p)]),
+    "amg_setup_host": (c_int, [POINTER(amg_problem), POINTER(amg_options), POINTER(c_void_p)]),
+    "amg_num_levels": (c_int, [c_void_p]),
+    "amg_level_info_get": (c_int, [c_void_p, c_int, POINTER(amg_level_info)]),
+    "amg_get_aggregates": (c_int, [c_void_p, c_int, POINTER(c_int32), POINTER(c_int32)]),
+    "amg_get_level_matrix": (
+        c_int,
+        [c_void_p, c_int, c_int, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), POINTER(c_int64),
+         POINTER(c_int32), POINTER(c_double)],
+    ),
+    "amg_update_fine_values": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "amg_apply_operator": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "amg_vcycle_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "fgmres_solve": (
+        c_int,
+        [c_void_p, c_int, c_void_p, c_void_p, POINTER(amg_gmres_options), POINTER(amg_gmres_result), c_void_p],
+    ),
+    "amg_grad_K": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "amg_profile_enable": (c_int, [c_void_p, c_int]),
+    "amg_profile_read": (c_int, [c_void_p, c_int, POINTER(c_int64), POINTER(c_double)]),
+    "amg_destroy": (None, [c_void_p]),
+    "amg_strerror": (c_char_p, [c_int]),
+    "amg_last_error": (c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = _LIB_PATH):
+    """Load libcamg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libcamg.so not found at {path}: build the HIP library first "
+            "(python -m paper_1912_09056_amd.build)"
+        )
+    lib = ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class CamgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcamg error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code < 0:
+        lib = load_library()
+        raise CamgError(code, f"{lib.amg_strerror(code).decode()} ({lib.amg_last_error().decode()})")
+    return code
+
+
+@dataclass
+class AMGOptions:
+    max_levels: int = 4
+    max_coarse_rows: int = 1000
+    nu_pre: int = 2
+    nu_post: int = 2
+    jacobi_sweeps: int = 1
+    atilde: int = 0
+    jacobi_diag: int = 0
+    precision: int = PREC_FP64
+    jacobi_omega: float = 0.8
+    simple_alpha: float = 0.8
+
+    def to_c(self) -> amg_options:
+        o = amg_options()
+        for f in amg_options._fields_:
+            setattr(o, f[0], getattr(self, f[0]))
+        return o
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(POINTER(ctype)) if a is not None and a.size else None
+
+
+def _csr_arrays(M, nrows, ncols):
+    """(rowptr int64, col int32, val float64) from a scipy-like CSR matrix."""
+    if M is None:
+        return np.zeros(nrows + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float64)
+    M = M.tocsr()
+    M.sort_indices()
+    assert M.shape == (nrows, ncols), (M.shape, nrows, ncols)
+    return (
+        np.ascontiguousarray(M.indptr, dtype=np.int64),
+        np.ascontiguousarray(M.indices, dtype=np.int32),
+        np.ascontiguousarray(M.data, dtype=np.float64),
+    )
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _dptr(t: torch.Tensor):
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return c_void_p(t.data_ptr())
+
+
+class AMGSolver:
+    """Owns one libcamg handle built from a contact problem.
+
+    K, G, B, C: scipy CSR matrices (host); slave_dofs / master_dofs: int
+    arrays of interface displacement dofs; nullspace: (n_u, n_ns) array.
+    """
+
+    def __init__(self, dim, K, G, B, C, slave_dofs, master_dofs, nullspace=None, lm_node=None,
+                 options: AMGOptions = None, device=None, host_only: bool = False):
+        self.lib = load_library()
+        self.host_only = host_only
+        if host_only:
+            self.device = None
+        else:
+            self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.options = options or AMGOptions()
+        n_u, n_l = K.shape[0], C.shape[0]
+        self.n_u, self.n_l, self.n = n_u, n_l, n_u + n_l
+        self.dim = dim
+        keep = []
+        prob = amg_problem()
+        prob.dim = dim
+        for name, M, r, c in (("K", K, n_u, n_u), ("G", G, n_u, n_l), ("B", B, n_l, n_u), ("C", C, n_l, n_l)):
+            rp, ci, v = _csr_arrays(M, r, c)
+            keep += [rp, ci, v]
+            setattr(prob, name, amg_csr(r, c, ci.size, _ptr(rp, c_int64), _ptr(ci, c_int32), _ptr(v, c_double)))
+        sd = np.ascontiguousarray(slave_dofs, dtype=np.int32)
+        md = np.ascontiguousarray(master_dofs, dtype=np.int32)
+        keep += [sd, md]
+        prob.n_slave, prob.n_master = sd.size, md.size
+        prob.slave_dofs, prob.master_dofs = _ptr(sd, c_int32), _ptr(md, c_int32)
+        if lm_node is not None:
+            ln = np.ascontiguousarray(lm_node, dtype=np.int32)
+            keep.append(ln)
+            prob.lm_node = _ptr(ln, c_int32)
+        if nullspace is not None:
+            ns = np.asfortranarray(nullspace, dtype=np.float64)
+            flat = np.ascontiguousarray(ns.reshape(-1, order="F"))
+            keep.append(flat)
+            prob.n_ns = ns.shape[1]
+            prob.nullspace = _ptr(flat, c_double)
+        self.K_nnz = keep[2].size
+        h = c_void_p()
+        opts = self.options.to_c()
+        if host_only:
+            _check(self.lib.amg_setup_host(byref(prob), byref(opts), byref(h)))
+        else:
+            with torch.cuda.device(self.device):
+                _check(self.lib.amg_setup(byref(prob), byref(opts), _stream_ptr(), byref(h)))
+        self.handle = h
+        self.n_levels = self.lib.amg_num_levels(h)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            try:
+                self.lib.amg_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+    @classmethod
+    def from_problem(cls, prob, options: AMGOptions = None, device=None, host_only: bool = False):
+        return cls(prob.dim, prob.K, prob.G, prob.B, prob.C, prob.slave_dofs, prob.master_dofs,
+                   nullspace=prob.nullspace, lm_node=prob.lm_node, options=options, device=device,
+                   host_only=host_only)
+
+    # ---- queries ---------------------------------------------------------
+    def level_info(self, level: int) -> dict:
+        info = amg_level_info()
+        _check(self.lib.amg_level_info_get(self.handle, level, byref(info)))
+        return {f[0]: getattr(info, f[0]) for f in amg_level_info._fields_}
+
+    def aggregates(self, level: int):
+        info = self.level_info(level)
+        du = np.zeros(info["n_nodes_u"], np.int32)
+        dl = np.zeros(info["n_nodes_l"], np.int32)
+        _check(self.lib.amg_get_aggregates(self.handle, level, _ptr(du, c_int32), _ptr(dl, c_int32)))
+        return du, dl
+
+    def level_matrix(self, level: int, which: str):
+        """Host copy of block K/G/B/C/P_u/P_l of a level as scipy CSR."""
+        import scipy.sparse as sp
+
+        w = {"K": 0, "G": 1, "B": 2, "C": 3, "P_u": 4, "P_l": 5}[which]
+        nr, nc, nz = c_int64(), c_int64(), c_int64()
+        _check(self.lib.amg_get_level_matrix(self.handle, level, w, byref(nr), byref(nc), byref(nz), None, None, None))
+        rp = np.zeros(nr.value + 1, np.int64)
+        ci = np.zeros(nz.value, np.int32)
+        v = np.zeros(nz.value, np.float64)
+        _check(self.lib.amg_get_level_matrix(self.handle, level, w, None, None, None, _ptr(rp, c_int64),
+                                             _ptr(ci, c_int32), _ptr(v, c_double)))
+        return sp.csr_matrix((v, ci, rp), shape=(nr.value, nc.value))
+
+    # ---- device work -------------------------------------------------------
+    def _vec(self, x):
+        if x is None:
+            return torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        t = torch.as_tensor(x, dtype=torch.float64, device=self.device)
+        return t.contiguous()
+
+    def apply_operator(self, x, transpose=False, stream=None):
+        x = self._vec(x)
+        y = torch.empty_like(x)
+        _check(self.lib.amg_apply_operator(self.handle, int(transpose), _dptr(x), _dptr(y), _stream_ptr(stream)))
+        return y
+
+    def vcycle(self, r, transpose=False, stream=None):
+        r = self._vec(r)
+        z = torch.empty_like(r)
+        _check(self.lib.amg_vcycle_apply(self.handle, int(transpose), _dptr(r), _dptr(z), _stream_ptr(stream)))
+        return z
+
+    def solve(self, b, x0=None, transpose=False, m=50, rtol=1e-8, max_iters=1000, fixed_iters=0, check_every=1,
+              stream=None):
+        """FGMRES solve; returns (x, result dict)."""
+        b = self._vec(b)
+        x = self._vec(x0).clone() if x0 is not None else torch.zeros_like(b)
+        go = amg_gmres_options(m, max_iters, fixed_iters, check_every, rtol)
+        res = amg_gmres_result()
+        code = _check(self.lib.fgmres_solve(self.handle, int(transpose), _dptr(b), _dptr(x), byref(go), byref(res),
+                                            _stream_ptr(stream)))
+        out = {f[0]: getattr(res, f[0]) for f in amg_gmres_result._fields_}
+        out["converged"] = code == CAMG_OK
+        return x, out
+
+    def grad_K(self, lam, x, stream=None):
+        lam, x = self._vec(lam), self._vec(x)
+        dK = torch.empty(self.K_nnz, dtype=torch.float64, device=self.device)
+        _check(self.lib.amg_grad_K(self.handle, _dptr(lam), _dptr(x), _dptr(dK), _stream_ptr(stream)))
+        return dK
+
+    def update_fine_values(self, K_val=None, G_val=None, B_val=None, C_val=None, stream=None):
+        args = []
+        keep = []
+        for v in (K_val, G_val, B_val, C_val):
+            if v is None:
+                args.append(None)
+            else:
+                t = torch.as_tensor(v, dtype=torch.float64, device=self.device).contiguous()
+                keep.append(t)
+                args.append(_dptr(t))
+        _check(self.lib.amg_update_fine_values(self.handle, *args, _stream_ptr(stream)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def profile_enable(self, mask: int):
+        _check(self.lib.amg_profile_enable(self.handle, mask))
+
+    def profile_read(self, kclass: int):
+        n, ms = c_int64(), c_double()
+        _check(self.lib.amg_profile_read(self.handle, kclass, byref(n), byref(ms)))
+        return n.value, ms.value
+
+
+def exported_symbols():
+    return list(SIGNATURES)

@@ -1,0 +1,89 @@
+// Shared HIP plumbing for libcamg: error propagation and device buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace camg {
+
+struct HipError {
+  hipError_t err;
+  std::string where;
+};
+
+#define CAMG_HIP(call)                                                             \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) throw ::camg::HipError{e_, std::string(#call) + " @ " + __FILE__ + ":" + std::to_string(__LINE__)}; \
+  } while (0)
+
+// Check for launch errors right after a kernel launch.
+#define CAMG_LAUNCHED() CAMG_HIP(hipGetLastError())
+
+struct OomError {
+  size_t bytes;
+};
+
+// Owning device allocation of n elements of T.
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  explicit DBuf(size_t count) { alloc(count); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return;
+    hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw OomError{count * sizeof(T)};
+    }
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const T* host, size_t count, hipStream_t s) {
+    if (count) CAMG_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void upload(const std::vector<T>& host, hipStream_t s) {
+    alloc(host.size());
+    upload(host.data(), host.size(), s);
+  }
+};
+
+// Device CSR view (int32 row pointers: nnz < 2^31 is checked at setup).
+template <typename T>
+struct DCSR {
+  int32_t nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  const int32_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const T* v = nullptr;
+};
+
+}  // namespace camg

@@ -1,0 +1,671 @@
+// Device kernels of libcamg for gfx950 (CDNA4, wave64).
+//
+// Sparse work is row-parallel CSR: a subgroup of SG lanes owns one row and
+// walks its column-index and value streams with unit stride, so the SG
+// lanes of a subgroup read contiguous bytes and neighbouring subgroups read
+// neighbouring rows.  Row sums are reduced inside the subgroup with
+// cross-lane shuffles.  No atomics anywhere: every output element has one
+// writer and every reduction has a fixed order, so results repeat bit for
+// bit from run to run.
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace camg {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T, int SG>
+__device__ __forceinline__ T sg_reduce(T v) {
+#pragma unroll
+  for (int off = SG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SG);
+  return v;
+}
+
+template <typename T, int SG>
+__device__ __forceinline__ T row_dot(const DCSR<T>& A, const T* __restrict__ x, int row, int lane) {
+  T s = T(0);
+  const int e = A.rp[row + 1];
+  for (int k = A.rp[row] + lane; k < e; k += SG) s += A.v[k] * x[A.ci[k]];
+  return s;
+}
+
+// Two products over one row with the same column stream: sum a_ij x_j and
+// sum a_ij (d_j * y_j).
+template <typename T, int SG>
+__device__ __forceinline__ void row_dot2(const DCSR<T>& A, const T* __restrict__ x, const T* __restrict__ d,
+                                         const T* __restrict__ y, int row, int lane, T& s1, T& s2) {
+  s1 = T(0);
+  s2 = T(0);
+  const int e = A.rp[row + 1];
+  for (int k = A.rp[row] + lane; k < e; k += SG) {
+    const int c = A.ci[k];
+    const T a = A.v[k];
+    s1 += a * x[c];
+    s2 += a * (d[c] * y[c]);
+  }
+}
+
+template <typename T, int SG, int MODE>
+__global__ void __launch_bounds__(kBlock) k_blk_spmv(DCSR<T> A11, DCSR<T> A12, DCSR<T> A21, DCSR<T> A22,
+                                                     const T* __restrict__ x1, const T* __restrict__ x2,
+                                                     const T* __restrict__ b1, const T* __restrict__ b2,
+                                                     T* __restrict__ y1, T* __restrict__ y2, int n1, int n) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n) return;  // uniform across the subgroup
+  T s = T(0);
+  if (row < n1) {
+    if (A11.nnz) s = row_dot<T, SG>(A11, x1, row, lane);
+    if (A12.nnz) s += row_dot<T, SG>(A12, x2, row, lane);
+  } else {
+    const int j = row - n1;
+    if (A21.nnz) s = row_dot<T, SG>(A21, x1, j, lane);
+    if (A22.nnz) s += row_dot<T, SG>(A22, x2, j, lane);
+  }
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) {
+    if (row < n1) {
+      if (MODE == 0) y1[row] = s;
+      else if (MODE == 1) y1[row] = b1[row] - s;
+      else y1[row] += s;
+    } else {
+      const int j = row - n1;
+      if (MODE == 0) y2[j] = s;
+      else if (MODE == 1) y2[j] = b2[j] - s;
+      else y2[j] += s;
+    }
+  }
+}
+
+template <typename T, int SG>
+__global__ void __launch_bounds__(kBlock) k_smooth_u(DCSR<T> K, DCSR<T> G, const T* __restrict__ zu,
+                                                     const T* __restrict__ zl, const T* __restrict__ bu,
+                                                     const T* __restrict__ jinv, T omega, T* __restrict__ znu,
+                                                     T* __restrict__ r_out, T* __restrict__ w_out, int n_u) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n_u) return;
+  T s = row_dot<T, SG>(K, zu, row, lane);
+  if (G.nnz) s += row_dot<T, SG>(G, zl, row, lane);
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) {
+    const T r = bu[row] - s;
+    const T w = omega * jinv[row] * r;
+    znu[row] = zu[row] + w;
+    if (r_out) {
+      r_out[row] = r;
+      w_out[row] = w;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth_u_first(const T* __restrict__ bu, const T* __restrict__ jinv,
+                                                           T omega, T* __restrict__ znu, T* __restrict__ r_out,
+                                                           T* __restrict__ w_out, int n_u) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_u) return;
+  const T r = bu[i];
+  const T w = omega * jinv[i] * r;
+  znu[i] = w;
+  if (r_out) {
+    r_out[i] = r;
+    w_out[i] = w;
+  }
+}
+
+template <typename T, int SG>
+__global__ void __launch_bounds__(kBlock) k_jacobi_extra(DCSR<T> M, const T* __restrict__ w, const T* __restrict__ r,
+                                                         const T* __restrict__ jinv, T omega, T* __restrict__ w_out,
+                                                         const T* __restrict__ zu, T* __restrict__ znu, int last,
+                                                         int n_u) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n_u) return;
+  T s = row_dot<T, SG>(M, w, row, lane);
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) {
+    const T wn = w[row] + omega * jinv[row] * (r[row] - s);
+    w_out[row] = wn;
+    if (last) znu[row] = (zu ? zu[row] : T(0)) + wn;
+  }
+}
+
+template <typename T, int SG, bool FIRST>
+__global__ void __launch_bounds__(kBlock) k_smooth_l(DCSR<T> B, DCSR<T> C, const T* __restrict__ znu,
+                                                     const T* __restrict__ zl, const T* __restrict__ bl,
+                                                     const T* __restrict__ sdinv, T alpha, T* __restrict__ znl,
+                                                     T* __restrict__ delta, int n_l) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n_l) return;
+  T s = T(0);
+  if (B.nnz) s = row_dot<T, SG>(B, znu, row, lane);
+  if (!FIRST && C.nnz) s += row_dot<T, SG>(C, zl, row, lane);
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) {
+    const T d = -(bl[row] - s) * sdinv[row];
+    delta[row] = d;
+    znl[row] = (FIRST ? T(0) : zl[row]) + alpha * d;
+  }
+}
+
+template <typename T, int SG>
+__global__ void __launch_bounds__(kBlock) k_correct_u(DCSR<T> G, const int32_t* __restrict__ rows, int n_rows,
+                                                      const T* __restrict__ delta, const T* __restrict__ ainv,
+                                                      T alpha, T* __restrict__ znu) {
+  const int idx = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (idx >= n_rows) return;
+  const int i = rows[idx];
+  T s = row_dot<T, SG>(G, delta, i, lane);
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) znu[i] -= alpha * ainv[i] * s;
+}
+
+template <typename T, int SG, bool FIRST>
+__global__ void __launch_bounds__(kBlock) k_tsmooth_u(DCSR<T> KT, DCSR<T> BT, const T* __restrict__ zu,
+                                                      const T* __restrict__ zl, const T* __restrict__ bu,
+                                                      T* __restrict__ su, int n_u) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n_u) return;
+  if (FIRST) {
+    if (lane == 0) su[row] = bu[row];
+    return;
+  }
+  T s = row_dot<T, SG>(KT, zu, row, lane);
+  if (BT.nnz) s += row_dot<T, SG>(BT, zl, row, lane);
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) su[row] = bu[row] - s;
+}
+
+template <typename T, int SG, bool FIRST>
+__global__ void __launch_bounds__(kBlock) k_tsmooth_l(DCSR<T> GT, DCSR<T> CT, const T* __restrict__ zu,
+                                                      const T* __restrict__ zl, const T* __restrict__ bl,
+                                                      const T* __restrict__ su, const T* __restrict__ ainv,
+                                                      const T* __restrict__ sdinv, T alpha, T* __restrict__ znl,
+                                                      T* __restrict__ delta, int n_l) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n_l) return;
+  T gz = T(0), gs = T(0), cz = T(0);
+  if (GT.nnz) row_dot2<T, SG>(GT, zu, ainv, su, row, lane, gz, gs);
+  if (!FIRST && CT.nnz) cz = row_dot<T, SG>(CT, zl, row, lane);
+  gz = sg_reduce<T, SG>(gz);
+  gs = sg_reduce<T, SG>(gs);
+  cz = sg_reduce<T, SG>(cz);
+  if (lane == 0) {
+    const T sl = FIRST ? bl[row] : bl[row] - gz - cz;
+    const T d = -(sl - gs) * sdinv[row];
+    delta[row] = d;
+    znl[row] = (FIRST ? T(0) : zl[row]) + alpha * d;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_tcorrect_u(DCSR<T> BT, const T* __restrict__ su,
+                                                       const T* __restrict__ delta, const T* __restrict__ jinv,
+                                                       T omega, T alpha, const T* __restrict__ zu,
+                                                       T* __restrict__ znu, T* __restrict__ t_out,
+                                                       T* __restrict__ w_out, int n_u) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_u) return;
+  T bd = T(0);
+  if (BT.nnz)
+    for (int k = BT.rp[i]; k < BT.rp[i + 1]; ++k) bd += BT.v[k] * delta[BT.ci[k]];
+  const T t = su[i] - alpha * bd;
+  const T w = omega * jinv[i] * t;
+  znu[i] = (zu ? zu[i] : T(0)) + w;
+  if (t_out) {
+    t_out[i] = t;
+    w_out[i] = w;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dense_gemv(const T* __restrict__ M, const T* __restrict__ x,
+                                                       T* __restrict__ y, int n) {
+  const int row = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= n) return;
+  const T* m = M + (int64_t)row * n;
+  T s = T(0);
+  for (int c = lane; c < n; c += 64) s += m[c] * x[c];
+  s = sg_reduce<T, 64>(s);
+  if (lane == 0) y[row] = s;
+}
+
+__global__ void k_cast_d2f(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+__global__ void k_cast_f2d(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+template <typename T>
+__global__ void k_copy(const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+template <typename T>
+__global__ void k_zero(T* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = T(0);
+}
+
+// ---- Krylov -----------------------------------------------------------------
+
+constexpr int kDotGroup = 8;
+
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = sg_reduce<double, 64>(v);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
+  return t;  // valid in thread 0
+}
+
+__global__ void __launch_bounds__(kBlock) k_mdot_partial(const double* __restrict__ V, int64_t ld, int kk,
+                                                         const double* __restrict__ w, int64_t n, int64_t chunk,
+                                                         double* __restrict__ partial, int nb) {
+  __shared__ double lds[kBlock / 64];
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(n, beg + chunk);
+  for (int k0 = 0; k0 < kk; k0 += kDotGroup) {
+    double acc[kDotGroup];
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) acc[q] = 0.0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+      const double wi = w[i];
+#pragma unroll
+      for (int q = 0; q < kDotGroup; ++q)
+        if (k0 + q < kk) acc[q] += V[(int64_t)(k0 + q) * ld + i] * wi;
+    }
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) {
+      if (k0 + q < kk) {
+        const double t = block_sum(acc[q], lds);
+        if (threadIdx.x == 0) partial[(int64_t)(k0 + q) * nb + blockIdx.x] = t;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_mdot_reduce(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ h) {
+  __shared__ double lds[kBlock / 64];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc += partial[(int64_t)k * nb + b];
+  const double t = block_sum(acc, lds);
+  if (threadIdx.x == 0) h[k] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_gemv_acc(const double* __restrict__ M, int64_t ld, int kk,
+                                                     const double* __restrict__ c, double sign,
+                                                     double* __restrict__ y, int64_t n) {
+  __shared__ double cs[512];
+  for (int k = threadIdx.x; k < kk; k += kBlock) cs[k] = c[k];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < kk; ++k) s += M[(int64_t)k * ld + i] * cs[k];
+  y[i] += sign * s;
+}
+
+__global__ void k_arnoldi_update(double* __restrict__ H, int ldh, double* __restrict__ cs, double* __restrict__ sn,
+                                 double* __restrict__ g, const double* __restrict__ h1,
+                                 const double* __restrict__ h2, const double* __restrict__ hn2, int j,
+                                 double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* col = H + (int64_t)j * ldh;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double hn = sqrt(hn2[0]);
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double d = hypot(a, b);
+  double c = 1.0, s = 0.0;
+  if (d != 0.0) {
+    c = a / d;
+    s = b / d;
+  }
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = d;
+  col[j + 1] = 0.0;
+  g[j + 1] = -s * g[j];
+  g[j] = c * g[j];
+  out[0] = fabs(g[j + 1]);
+  out[1] = hn;
+  out[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_restart_init(const double* __restrict__ r,
+                                                         const double* __restrict__ beta2, double* __restrict__ V0,
+                                                         double* __restrict__ g, int gl, double* __restrict__ out,
+                                                         int64_t n) {
+  const double beta = sqrt(beta2[0]);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) V0[i] = r[i] * inv;
+  if (i < gl) g[i] = (i == 0) ? beta : 0.0;
+  if (i == 0) out[0] = beta;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale_by(const double* __restrict__ x, const double* __restrict__ scale,
+                                                     double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = x[i] * scale[0];
+}
+
+__global__ void k_hess_solve(const double* __restrict__ H, int ldh, const double* __restrict__ g,
+                             double* __restrict__ y, int k) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int l = i + 1; l < k; ++l) s -= H[(int64_t)l * ldh + i] * y[l];
+    y[i] = s / H[(int64_t)i * ldh + i];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_grad_K(DCSR<double> K, const double* __restrict__ lam,
+                                                   const double* __restrict__ x, double* __restrict__ dK) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= K.nrows) return;
+  const double li = lam[i];
+  for (int k = K.rp[i]; k < K.rp[i + 1]; ++k) dK[k] = -li * x[K.ci[k]];
+}
+
+template <typename T>
+__global__ void k_scatter_perm(const double* __restrict__ src, const int32_t* __restrict__ perm, T* __restrict__ dst,
+                               int64_t nnz) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < nnz) dst[perm[e]] = (T)src[e];
+}
+
+template <typename T>
+__global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, int64_t nnz) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < nnz) dst[e] = (T)src[e];
+}
+
+inline unsigned grid_for(int64_t rows, int rows_per_block) {
+  return (unsigned)((rows + rows_per_block - 1) / rows_per_block);
+}
+
+}  // namespace
+
+int pick_subgroup(int64_t nnz, int64_t nrows) {
+  const double avg = nrows ? (double)nnz / (double)nrows : 0.0;
+  if (avg > 96.0) return 64;
+  if (avg > 40.0) return 32;
+  if (avg > 14.0) return 16;
+  if (avg > 5.0) return 8;
+  return 4;
+}
+
+#define CAMG_SG_DISPATCH(sg, ...) \
+  switch (sg) {                           \
+    case 4: {                             \
+      constexpr int SG = 4;               \
+      __VA_ARGS__;                        \
+    } break;                              \
+    case 8: {                             \
+      constexpr int SG = 8;               \
+      __VA_ARGS__;                        \
+    } break;                              \
+    case 16: {                            \
+      constexpr int SG = 16;              \
+      __VA_ARGS__;                        \
+    } break;                              \
+    case 32: {                            \
+      constexpr int SG = 32;              \
+      __VA_ARGS__;                        \
+    } break;                              \
+    default: {                            \
+      constexpr int SG = 64;              \
+      __VA_ARGS__;                        \
+    } break;                              \
+  }
+
+template <typename T>
+void blk_spmv(const DCSR<T>& A11, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22, const T* x1,
+              const T* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2, int mode, int sg,
+              hipStream_t s) {
+  const int n = n1 + n2;
+  if (n <= 0) return;
+  CAMG_SG_DISPATCH(sg, {
+    dim3 grid(grid_for(n, kBlock / SG));
+    if (mode == 0)
+      k_blk_spmv<T, SG, 0><<<grid, kBlock, 0, s>>>(A11, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n);
+    else if (mode == 1)
+      k_blk_spmv<T, SG, 1><<<grid, kBlock, 0, s>>>(A11, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n);
+    else
+      k_blk_spmv<T, SG, 2><<<grid, kBlock, 0, s>>>(A11, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n);
+  });
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void smooth_u(const DCSR<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* jinv, T omega,
+              T* znu, T* r_out, T* w_out, int n_u, bool first, int sg, hipStream_t s) {
+  if (n_u <= 0) return;
+  if (first) {
+    k_smooth_u_first<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(bu, jinv, omega, znu, r_out, w_out, n_u);
+  } else {
+    CAMG_SG_DISPATCH(sg, {
+      k_smooth_u<T, SG><<<grid_for(n_u, kBlock / SG), kBlock, 0, s>>>(K, G, zu, zl, bu, jinv, omega, znu, r_out,
+                                                                      w_out, n_u);
+    });
+  }
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void jacobi_extra(const DCSR<T>& M, const T* w, const T* r, const T* jinv, T omega, T* w_out, const T* zu, T* znu,
+                  bool last, int n_u, int sg, hipStream_t s) {
+  if (n_u <= 0) return;
+  CAMG_SG_DISPATCH(sg, {
+    k_jacobi_extra<T, SG><<<grid_for(n_u, kBlock / SG), kBlock, 0, s>>>(M, w, r, jinv, omega, w_out, zu, znu,
+                                                                         last ? 1 : 0, n_u);
+  });
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void smooth_l(const DCSR<T>& B, const DCSR<T>& C, const T* znu, const T* zl, const T* bl, const T* sdinv, T alpha,
+              T* znl, T* delta, int n_l, bool first, hipStream_t s) {
+  if (n_l <= 0) return;
+  constexpr int SG = 8;
+  dim3 grid(grid_for(n_l, kBlock / SG));
+  if (first)
+    k_smooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, n_l);
+  else
+    k_smooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, n_l);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void correct_u(const DCSR<T>& G, const int32_t* rows, int n_rows, const T* delta, const T* ainv, T alpha, T* znu,
+               hipStream_t s) {
+  if (n_rows <= 0) return;
+  constexpr int SG = 4;
+  k_correct_u<T, SG><<<grid_for(n_rows, kBlock / SG), kBlock, 0, s>>>(G, rows, n_rows, delta, ainv, alpha, znu);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void tsmooth_u(const DCSR<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, const T* bu, T* su, int n_u,
+               bool first, int sg, hipStream_t s) {
+  if (n_u <= 0) return;
+  if (first) {
+    k_copy<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(bu, su, n_u);
+  } else {
+    CAMG_SG_DISPATCH(sg, {
+      k_tsmooth_u<T, SG, false><<<grid_for(n_u, kBlock / SG), kBlock, 0, s>>>(KT, BT, zu, zl, bu, su, n_u);
+    });
+  }
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void tsmooth_l(const DCSR<T>& GT, const DCSR<T>& CT, const T* zu, const T* zl, const T* bl, const T* su,
+               const T* ainv, const T* sdinv, T alpha, T* znl, T* delta, int n_l, bool first, hipStream_t s) {
+  if (n_l <= 0) return;
+  constexpr int SG = 16;
+  dim3 grid(grid_for(n_l, kBlock / SG));
+  if (first)
+    k_tsmooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta, n_l);
+  else
+    k_tsmooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta, n_l);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void tcorrect_u(const DCSR<T>& BT, const T* su, const T* delta, const T* jinv, T omega, T alpha, const T* zu,
+                T* znu, T* t_out, T* w_out, int n_u, bool first, hipStream_t s) {
+  if (n_u <= 0) return;
+  k_tcorrect_u<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(BT, su, delta, jinv, omega, alpha, first ? nullptr : zu,
+                                                           znu, t_out, w_out, n_u);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void dense_gemv(const T* M, const T* x, T* y, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_dense_gemv<T><<<grid_for(n, kBlock / 64), kBlock, 0, s>>>(M, x, y, n);
+  CAMG_LAUNCHED();
+}
+
+void cast_d2f(const double* x, float* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast_d2f<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, y, n);
+  CAMG_LAUNCHED();
+}
+void cast_f2d(const float* x, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast_f2d<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, y, n);
+  CAMG_LAUNCHED();
+}
+template <typename T>
+void copy_vec(const T* x, T* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_copy<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(x, y, n);
+  CAMG_LAUNCHED();
+}
+template <typename T>
+void zero_vec(T* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_zero<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(y, n);
+  CAMG_LAUNCHED();
+}
+
+int mdot_blocks(int64_t n) {
+  int64_t nb = (n + 511) / 512;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(2048, nb));
+}
+
+void mdot(const double* V, int64_t ld, int kk, const double* w, int64_t n, double* partial, double* h,
+          hipStream_t s) {
+  if (kk <= 0) return;
+  const int nb = mdot_blocks(n);
+  const int64_t chunk = (n + nb - 1) / nb;
+  k_mdot_partial<<<nb, kBlock, 0, s>>>(V, ld, kk, w, n, chunk, partial, nb);
+  CAMG_LAUNCHED();
+  k_mdot_reduce<<<kk, kBlock, 0, s>>>(partial, nb, h);
+  CAMG_LAUNCHED();
+}
+
+void gemv_acc(const double* M, int64_t ld, int kk, const double* c, double sign, double* y, int64_t n,
+              hipStream_t s) {
+  if (kk <= 0 || n <= 0) return;
+  k_gemv_acc<<<grid_for(n, kBlock), kBlock, 0, s>>>(M, ld, kk, c, sign, y, n);
+  CAMG_LAUNCHED();
+}
+
+void arnoldi_update(double* H, int ldh, double* cs, double* sn, double* g, const double* h1, const double* h2,
+                    const double* hn2, int j, double* out, hipStream_t s) {
+  k_arnoldi_update<<<1, 64, 0, s>>>(H, ldh, cs, sn, g, h1, h2, hn2, j, out);
+  CAMG_LAUNCHED();
+}
+
+void restart_init(const double* r, const double* beta2, double* V0, double* g, int gl, double* out, int64_t n,
+                  hipStream_t s) {
+  const int64_t m = std::max<int64_t>(n, gl);
+  k_restart_init<<<grid_for(m, kBlock), kBlock, 0, s>>>(r, beta2, V0, g, gl, out, n);
+  CAMG_LAUNCHED();
+}
+
+void scale_by(const double* x, const double* scale, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_scale_by<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, scale, y, n);
+  CAMG_LAUNCHED();
+}
+
+void hess_solve(const double* H, int ldh, const double* g, double* y, int k, hipStream_t s) {
+  if (k <= 0) return;
+  k_hess_solve<<<1, 64, 0, s>>>(H, ldh, g, y, k);
+  CAMG_LAUNCHED();
+}
+
+void grad_K(const DCSR<double>& K, const double* lam, const double* x, double* dK, hipStream_t s) {
+  if (K.nrows <= 0) return;
+  k_grad_K<<<grid_for(K.nrows, kBlock), kBlock, 0, s>>>(K, lam, x, dK);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void scatter_perm(const double* src, const int32_t* perm, T* dst, int64_t nnz, hipStream_t s) {
+  if (nnz <= 0) return;
+  k_scatter_perm<T><<<grid_for(nnz, kBlock), kBlock, 0, s>>>(src, perm, dst, nnz);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
+  if (nnz <= 0) return;
+  k_convert<T><<<grid_for(nnz, kBlock), kBlock, 0, s>>>(src, dst, nnz);
+  CAMG_LAUNCHED();
+}
+
+#define CAMG_INSTANTIATE(T)                                                                                        \
+  template void blk_spmv<T>(const DCSR<T>&, const DCSR<T>&, const DCSR<T>&, const DCSR<T>&, const T*, const T*,   \
+                            const T*, const T*, T*, T*, int, int, int, int, hipStream_t);                         \
+  template void smooth_u<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T, T*, T*, T*, \
+                            int, bool, int, hipStream_t);                                                          \
+  template void jacobi_extra<T>(const DCSR<T>&, const T*, const T*, const T*, T, T*, const T*, T*, bool, int, int, \
+                                hipStream_t);                                                                      \
+  template void smooth_l<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T, T*, T*, int, \
+                            bool, hipStream_t);                                                                    \
+  template void correct_u<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, hipStream_t);         \
+  template void tsmooth_u<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, T*, int, bool, int,      \
+                             hipStream_t);                                                                         \
+  template void tsmooth_l<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, const T*,      \
+                             const T*, T, T*, T*, int, bool, hipStream_t);                                         \
+  template void tcorrect_u<T>(const DCSR<T>&, const T*, const T*, const T*, T, T, const T*, T*, T*, T*, int, bool,  \
+                              hipStream_t);                                                                        \
+  template void dense_gemv<T>(const T*, const T*, T*, int, hipStream_t);                                           \
+  template void copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                                   \
+  template void zero_vec<T>(T*, int64_t, hipStream_t);                                                             \
+  template void scatter_perm<T>(const double*, const int32_t*, T*, int64_t, hipStream_t);                          \
+  template void convert_vals<T>(const double*, T*, int64_t, hipStream_t);
+
+CAMG_INSTANTIATE(float)
+CAMG_INSTANTIATE(double)
+
+}  // namespace camg

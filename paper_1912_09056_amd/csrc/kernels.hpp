@@ -1,0 +1,110 @@
+// Launch wrappers for the libcamg device kernels (gfx950, wave64).
+//
+// All kernels are deterministic: no atomics, fixed reduction trees, one
+// writer per output element.  Sparse kernels are row-parallel CSR with a
+// subgroup of `sg` lanes per row (4..64) whose column/value streams are
+// read contiguously by the subgroup.
+#pragma once
+
+#include "common.hpp"
+
+namespace camg {
+
+// sg: lanes per row, chosen from the dominant block's mean row length.
+int pick_subgroup(int64_t nnz, int64_t nrows);
+
+// Two-by-two block row SpMV over rows [0, n1) -> (A11 x1 + A12 x2) and rows
+// [n1, n1 + n2) -> (A21 x1 + A22 x2).  Empty blocks (nnz = 0) are skipped.
+//   mode 0: y = A x     mode 1: y = b - A x     mode 2: y += A x
+template <typename T>
+void blk_spmv(const DCSR<T>& A11, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22, const T* x1,
+              const T* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2, int mode, int sg,
+              hipStream_t s);
+
+// CheapSIMPLE forward sweep, displacement rows: r = b_u - K z_u - G z_l,
+// w = omega * jinv * r, zn_u = z_u + w.  first: z = 0 (no SpMV).
+// If r_out / w_out are non-null they receive r and w (extra Jacobi sweeps).
+template <typename T>
+void smooth_u(const DCSR<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* jinv, T omega,
+              T* znu, T* r_out, T* w_out, int n_u, bool first, int sg, hipStream_t s);
+
+// Extra damped-Jacobi sweep on M w = r: w_out = w + omega*jinv*(r - M w);
+// when last, also zn_u = z_u + w_out (z_u null: zn_u = w_out).
+template <typename T>
+void jacobi_extra(const DCSR<T>& M, const T* w, const T* r, const T* jinv, T omega, T* w_out, const T* zu, T* znu,
+                  bool last, int n_u, int sg, hipStream_t s);
+
+// CheapSIMPLE forward sweep, multiplier rows: rt = b_l - B zn_u - C z_l,
+// delta = -rt * sdinv, zn_l = z_l + alpha * delta.  first: z_l = 0.
+template <typename T>
+void smooth_l(const DCSR<T>& B, const DCSR<T>& C, const T* znu, const T* zl, const T* bl, const T* sdinv, T alpha,
+              T* znl, T* delta, int n_l, bool first, hipStream_t s);
+
+// zn_u[i] -= alpha * ainv[i] * (G delta)[i] for the listed rows of G.
+template <typename T>
+void correct_u(const DCSR<T>& G, const int32_t* rows, int n_rows, const T* delta, const T* ainv, T alpha, T* znu,
+               hipStream_t s);
+
+// Adjoint sweep, step 1: s_u = b_u - K^T z_u - B^T z_l (first: s_u = b_u).
+template <typename T>
+void tsmooth_u(const DCSR<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, const T* bu, T* su, int n_u,
+               bool first, int sg, hipStream_t s);
+
+// Adjoint sweep, step 2: s_l = b_l - G^T z_u - C^T z_l,
+// delta = -(s_l - G^T (ainv .* s_u)) * sdinv, zn_l = z_l + alpha * delta.
+template <typename T>
+void tsmooth_l(const DCSR<T>& GT, const DCSR<T>& CT, const T* zu, const T* zl, const T* bl, const T* su,
+               const T* ainv, const T* sdinv, T alpha, T* znl, T* delta, int n_l, bool first, hipStream_t s);
+
+// Adjoint sweep, step 3: t = s_u - alpha * B^T delta, w = omega*jinv*t,
+// zn_u = z_u + w (first: z_u = 0).  t_out / w_out optional.
+template <typename T>
+void tcorrect_u(const DCSR<T>& BT, const T* su, const T* delta, const T* jinv, T omega, T alpha, const T* zu,
+                T* znu, T* t_out, T* w_out, int n_u, bool first, hipStream_t s);
+
+// y = M x for a dense row-major n x n matrix (coarsest level).
+template <typename T>
+void dense_gemv(const T* M, const T* x, T* y, int n, hipStream_t s);
+
+// Elementwise helpers.
+void cast_d2f(const double* x, float* y, int64_t n, hipStream_t s);
+void cast_f2d(const float* x, double* y, int64_t n, hipStream_t s);
+template <typename T>
+void copy_vec(const T* x, T* y, int64_t n, hipStream_t s);
+template <typename T>
+void zero_vec(T* y, int64_t n, hipStream_t s);
+
+// ---- FP64 Krylov kernels --------------------------------------------------
+// Number of partial-sum blocks used by mdot for a vector length n.
+int mdot_blocks(int64_t n);
+// h[k] = sum_i V[k*ld + i] * w[i] for k < kk (two-stage, fixed order).
+// partial must hold kk * mdot_blocks(n) doubles.
+void mdot(const double* V, int64_t ld, int kk, const double* w, int64_t n, double* partial, double* h,
+          hipStream_t s);
+// y[i] += sign * sum_k M[k*ld + i] * c[k]  (c on device)
+void gemv_acc(const double* M, int64_t ld, int kk, const double* c, double sign, double* y, int64_t n,
+              hipStream_t s);
+// Arnoldi column j: H[:, j] = h1 + h2 (kk = j + 1 entries), H[j+1, j] =
+// sqrt(*hn2); apply the previous Givens rotations, build rotation j, update
+// g.  out[0] = |g[j+1]|, out[1] = H[j+1,j] before rotation, out[2] = 1/out[1]
+// (0 when it vanishes).
+void arnoldi_update(double* H, int ldh, double* cs, double* sn, double* g, const double* h1, const double* h2,
+                    const double* hn2, int j, double* out, hipStream_t s);
+// V0 = r * (1 / sqrt(*beta2)); g = [sqrt(*beta2), 0, ...]; out[0] = sqrt(*beta2)
+void restart_init(const double* r, const double* beta2, double* V0, double* g, int gl, double* out, int64_t n,
+                  hipStream_t s);
+// y = x * (*scale)
+void scale_by(const double* x, const double* scale, double* y, int64_t n, hipStream_t s);
+// Back substitution H(0:k,0:k) y = g(0:k).
+void hess_solve(const double* H, int ldh, const double* g, double* y, int k, hipStream_t s);
+
+// dK[e] = -lam[row(e)] * x[col(e)] over the entries of K.
+void grad_K(const DCSR<double>& K, const double* lam, const double* x, double* dK, hipStream_t s);
+// dst[perm[e]] = src[e] (value refresh of an explicit transpose).
+template <typename T>
+void scatter_perm(const double* src, const int32_t* perm, T* dst, int64_t nnz, hipStream_t s);
+// dst[e] = (T) src[e]
+template <typename T>
+void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s);
+
+}  // namespace camg

@@ -1,0 +1,492 @@
+// Host construction of the fully coupled aggregation-AMG hierarchy for the
+// mortar-contact saddle-point system (Sec. 4 of the paper; smoother data of
+// Sec. 5.1.3; merged direct solve on the coarsest level as in the
+// weak-scaling study's solver settings).
+//
+// Readings taken where the paper leaves details open:
+//  * Dirichlet dof: a K row whose only stored entry is its diagonal and whose
+//    G row is empty.  Nodes with all dofs Dirichlet are not aggregated; the
+//    null-space rows of Dirichlet dofs are zero, so are their P rows.
+//  * Node graph: stored K entries between non-Dirichlet dofs of different
+//    nodes; pairs (slave interface node, master interface node) dropped
+//    (Sec. 4.2).
+//  * Aggregation: three greedy phases in natural node order -- roots whose
+//    neighbourhood is untouched take all neighbours; leftovers join the
+//    adjacent phase-1 aggregate with most neighbours (snapshot, ties to the
+//    smallest id); remaining nodes seed aggregates with their free
+//    neighbours.
+//  * Alg. 1: slave displacement dofs in ascending order, "D_ij != 0" is a
+//    stored entry of G's slave row; a pseudo-node keeps its first aggregate.
+//  * Tentative transfers: per-aggregate modified Gram-Schmidt QR of the
+//    null-space rows (ascending dof order, columns in order, R_kk > 0); the
+//    pattern of P holds all n_ns coarse columns of the aggregate for every
+//    contributing fine dof (explicit zeros kept); the multiplier null space
+//    is one constant per Cartesian component.
+//  * Galerkin blocks on the symbolic pattern of R A P (no dropping).
+//  * Coarse interface nodes: aggregates containing interface nodes.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace camg {
+
+namespace {
+
+[[noreturn]] void fail(int code, const std::string& m) { throw SetupError{code, m}; }
+
+constexpr int kErrZeroDiag = -4;
+constexpr int kErrRankDeficient = -5;
+constexpr int kErrSingularCoarse = -6;
+constexpr int kErrUnmapped = -9;
+
+std::vector<uint8_t> find_dirichlet(const HostCSR& K, const HostCSR& G) {
+  std::vector<uint8_t> d((size_t)K.nrows, 0);
+  for (int64_t i = 0; i < K.nrows; ++i) {
+    int64_t a = K.rp[i], b = K.rp[i + 1];
+    bool only_diag = (b - a == 1) && K.ci[a] == i;
+    bool g_empty = G.rp[i + 1] == G.rp[i];
+    d[i] = (only_diag && g_empty) ? 1 : 0;
+  }
+  return d;
+}
+
+// Node adjacency as CSR (sorted, unique, no self loops).
+void node_graph(const HostLevel& L, std::vector<int64_t>& gp, std::vector<int32_t>& gi) {
+  const int bs = L.bs_u;
+  const int64_t nn = L.n_u() / bs;
+  gp.assign((size_t)nn + 1, 0);
+  gi.clear();
+  std::vector<int64_t> mark((size_t)nn, -1);
+  std::vector<int32_t> row;
+  for (int64_t a = 0; a < nn; ++a) {
+    row.clear();
+    for (int c = 0; c < bs; ++c) {
+      int64_t r = a * bs + c;
+      if (L.dirichlet[r]) continue;
+      for (int64_t k = L.K.rp[r]; k < L.K.rp[r + 1]; ++k) {
+        int32_t col = L.K.ci[k];
+        if (L.dirichlet[col]) continue;
+        int64_t b = col / bs;
+        if (b == a) continue;
+        if ((L.slave_node[a] && L.master_node[b]) || (L.master_node[a] && L.slave_node[b])) continue;
+        if (mark[b] != a) {
+          mark[b] = a;
+          row.push_back((int32_t)b);
+        }
+      }
+    }
+    std::sort(row.begin(), row.end());
+    gi.insert(gi.end(), row.begin(), row.end());
+    gp[a + 1] = (int64_t)gi.size();
+  }
+}
+
+int64_t aggregate_nodes(const std::vector<int64_t>& gp, const std::vector<int32_t>& gi,
+                        const std::vector<uint8_t>& active, std::vector<int32_t>& agg) {
+  const int64_t n = (int64_t)active.size();
+  agg.assign((size_t)n, -1);
+  int64_t n_agg = 0;
+  // phase 1: roots with untouched neighbourhoods
+  for (int64_t i = 0; i < n; ++i) {
+    if (!active[i] || agg[i] >= 0) continue;
+    bool free_nbhd = true;
+    for (int64_t k = gp[i]; k < gp[i + 1]; ++k) {
+      int32_t j = gi[k];
+      if (active[j] && agg[j] >= 0) {
+        free_nbhd = false;
+        break;
+      }
+    }
+    if (!free_nbhd) continue;
+    agg[i] = (int32_t)n_agg;
+    for (int64_t k = gp[i]; k < gp[i + 1]; ++k)
+      if (active[gi[k]]) agg[gi[k]] = (int32_t)n_agg;
+    ++n_agg;
+  }
+  // phase 2: attach leftovers to the most connected phase-1 aggregate
+  std::vector<int32_t> snap = agg;
+  std::vector<int32_t> cand;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!active[i] || snap[i] >= 0) continue;
+    cand.clear();
+    for (int64_t k = gp[i]; k < gp[i + 1]; ++k) {
+      int32_t j = gi[k];
+      if (active[j] && snap[j] >= 0) cand.push_back(snap[j]);
+    }
+    if (cand.empty()) continue;
+    std::sort(cand.begin(), cand.end());
+    int32_t best = cand[0];
+    int best_cnt = 0;
+    for (size_t s = 0; s < cand.size();) {
+      size_t e = s;
+      while (e < cand.size() && cand[e] == cand[s]) ++e;
+      int cnt = (int)(e - s);
+      if (cnt > best_cnt) {  // strict: equal counts keep the smaller id
+        best_cnt = cnt;
+        best = cand[s];
+      }
+      s = e;
+    }
+    agg[i] = best;
+  }
+  // phase 3: leftovers seed new aggregates with their free neighbours
+  for (int64_t i = 0; i < n; ++i) {
+    if (!active[i] || agg[i] >= 0) continue;
+    agg[i] = (int32_t)n_agg;
+    for (int64_t k = gp[i]; k < gp[i + 1]; ++k) {
+      int32_t j = gi[k];
+      if (active[j] && agg[j] < 0) agg[j] = (int32_t)n_agg;
+    }
+    ++n_agg;
+  }
+  return n_agg;
+}
+
+// Alg. 1 of the paper (Sec. 4.3).
+int64_t lagmult_aggregation(const HostLevel& L, std::vector<int32_t>& agg_l) {
+  const int bs = L.bs_u;
+  agg_l.assign((size_t)L.n_nodes_l, -1);
+  std::vector<int32_t> dmap((size_t)L.n_agg_u, -1);
+  int64_t count = 0;
+  const int64_t nn = L.n_u() / bs;
+  for (int64_t node = 0; node < nn; ++node) {
+    if (!L.slave_node[node]) continue;
+    for (int c = 0; c < bs; ++c) {  // ascending slave dofs
+      int64_t i = node * bs + c;
+      int32_t k = L.agg_u[node];
+      if (k < 0) continue;
+      for (int64_t e = L.G.rp[i]; e < L.G.rp[i + 1]; ++e) {
+        if (dmap[k] < 0) dmap[k] = (int32_t)count++;
+        int32_t pn = L.lm_node[L.G.ci[e]];
+        if (agg_l[pn] < 0) agg_l[pn] = dmap[k];
+      }
+    }
+  }
+  for (int64_t p = 0; p < L.n_nodes_l; ++p)
+    if (agg_l[p] < 0) fail(kErrUnmapped, "multiplier pseudo-node coupled to no slave displacement dof");
+  return count;
+}
+
+// Tentative prolongator by per-aggregate modified Gram-Schmidt.
+// node_of(r) gives the node of fine row r (or -1), zero(r) marks zeroed rows.
+template <class NodeOf, class Zero>
+void tentative(int64_t n_rows, int n_ns, const std::vector<double>& ns, const std::vector<int32_t>& agg,
+               int64_t n_agg, NodeOf node_of, Zero zero, HostCSR& P, std::vector<double>& ns_coarse) {
+  std::vector<int32_t> row_agg((size_t)n_rows, -1);
+  std::vector<int64_t> cnt((size_t)n_agg + 1, 0);
+  for (int64_t r = 0; r < n_rows; ++r) {
+    int64_t nd = node_of(r);
+    if (nd < 0 || zero(r)) continue;
+    int32_t a = agg[nd];
+    if (a < 0) continue;
+    row_agg[r] = a;
+    cnt[a + 1]++;
+  }
+  for (int64_t a = 0; a < n_agg; ++a) cnt[a + 1] += cnt[a];
+  std::vector<int64_t> rows((size_t)cnt[n_agg]);
+  {
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t r = 0; r < n_rows; ++r)
+      if (row_agg[r] >= 0) rows[pos[row_agg[r]]++] = r;  // ascending within each aggregate
+  }
+  std::vector<double> Pv((size_t)n_rows * n_ns, 0.0);
+  const int64_t nc = n_agg * n_ns;
+  ns_coarse.assign((size_t)nc * n_ns, 0.0);  // column-major, nc rows
+  std::vector<double> Q, R((size_t)n_ns * n_ns);
+  for (int64_t a = 0; a < n_agg; ++a) {
+    const int64_t m = cnt[a + 1] - cnt[a];
+    const int64_t* rr = rows.data() + cnt[a];
+    Q.assign((size_t)m * n_ns, 0.0);  // column-major m x n_ns
+    std::fill(R.begin(), R.end(), 0.0);
+    for (int k = 0; k < n_ns; ++k) {
+      double* v = Q.data() + (size_t)k * m;
+      double orig = 0.0;
+      for (int64_t s = 0; s < m; ++s) {
+        v[s] = ns[(size_t)k * n_rows + rr[s]];
+        orig += v[s] * v[s];
+      }
+      for (int i = 0; i < k; ++i) {
+        const double* q = Q.data() + (size_t)i * m;
+        double dot = 0.0;
+        for (int64_t s = 0; s < m; ++s) dot += q[s] * v[s];
+        R[(size_t)i * n_ns + k] = dot;
+        for (int64_t s = 0; s < m; ++s) v[s] -= dot * q[s];
+      }
+      double nv = 0.0;
+      for (int64_t s = 0; s < m; ++s) nv += v[s] * v[s];
+      nv = std::sqrt(nv);
+      if (!(nv > 1e-12 * std::sqrt(orig))) fail(kErrRankDeficient, "null space rank-deficient on an aggregate");
+      R[(size_t)k * n_ns + k] = nv;
+      for (int64_t s = 0; s < m; ++s) v[s] /= nv;
+    }
+    for (int64_t s = 0; s < m; ++s)
+      for (int k = 0; k < n_ns; ++k) Pv[(size_t)rr[s] * n_ns + k] = Q[(size_t)k * m + s];
+    for (int i = 0; i < n_ns; ++i)
+      for (int k = 0; k < n_ns; ++k) ns_coarse[(size_t)k * nc + a * n_ns + i] = R[(size_t)i * n_ns + k];
+  }
+  P.init_empty(n_rows, nc);
+  for (int64_t r = 0; r < n_rows; ++r) {
+    if (row_agg[r] >= 0) {
+      for (int k = 0; k < n_ns; ++k) {
+        P.ci.push_back(row_agg[r] * n_ns + k);
+        P.v.push_back(Pv[(size_t)r * n_ns + k]);
+      }
+    }
+    P.rp[r + 1] = P.nnz();
+  }
+}
+
+// R A P on the symbolic pattern.  Consecutive rows of R with identical
+// column sets (the rows of one aggregate) share one pass over A P.
+HostCSR galerkin(const HostCSR& R, const HostCSR& A, const HostCSR& P) {
+  HostCSR out;
+  out.init_empty(R.nrows, P.ncols);
+  std::vector<int32_t> loc((size_t)P.ncols, -1);
+  std::vector<int32_t> touched;
+  std::vector<int32_t> fine;
+  std::vector<double> tmp;  // fine.size() x touched.size()
+  int64_t r0 = 0;
+  while (r0 < R.nrows) {
+    int64_t r1 = r0 + 1;
+    auto same = [&](int64_t a, int64_t b) {
+      int64_t la = R.rp[a + 1] - R.rp[a], lb = R.rp[b + 1] - R.rp[b];
+      if (la != lb) return false;
+      return std::equal(R.ci.begin() + R.rp[a], R.ci.begin() + R.rp[a + 1], R.ci.begin() + R.rp[b]);
+    };
+    while (r1 < R.nrows && same(r0, r1)) ++r1;
+    fine.assign(R.ci.begin() + R.rp[r0], R.ci.begin() + R.rp[r0 + 1]);
+    touched.clear();
+    for (int32_t i : fine)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        int32_t j = A.ci[k];
+        for (int64_t q = P.rp[j]; q < P.rp[j + 1]; ++q) {
+          int32_t c = P.ci[q];
+          if (loc[c] < 0) {
+            loc[c] = (int32_t)touched.size();
+            touched.push_back(c);
+          }
+        }
+      }
+    std::sort(touched.begin(), touched.end());
+    for (size_t t = 0; t < touched.size(); ++t) loc[touched[t]] = (int32_t)t;
+    const size_t nt = touched.size();
+    tmp.assign(fine.size() * nt, 0.0);
+    for (size_t f = 0; f < fine.size(); ++f) {
+      int32_t i = fine[f];
+      double* trow = tmp.data() + f * nt;
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        int32_t j = A.ci[k];
+        double a = A.v[k];
+        for (int64_t q = P.rp[j]; q < P.rp[j + 1]; ++q) trow[loc[P.ci[q]]] += a * P.v[q];
+      }
+    }
+    for (int64_t r = r0; r < r1; ++r) {
+      size_t base = out.ci.size();
+      out.ci.insert(out.ci.end(), touched.begin(), touched.end());
+      out.v.resize(base + nt, 0.0);
+      double* orow = out.v.data() + base;
+      int64_t f = 0;
+      for (int64_t k = R.rp[r]; k < R.rp[r + 1]; ++k, ++f) {
+        double w = R.v[k];
+        const double* trow = tmp.data() + (size_t)f * nt;
+        for (size_t t = 0; t < nt; ++t) orow[t] += w * trow[t];
+      }
+      out.rp[r + 1] = out.nnz();
+    }
+    for (int32_t c : touched) loc[c] = -1;
+    r0 = r1;
+  }
+  return out;
+}
+
+void smoother_data(HostLevel& L, const SetupOptions& opt) {
+  const int64_t nu = L.n_u(), nl = L.n_l();
+  std::vector<double> at((size_t)nu), dg((size_t)nu, 0.0);
+  for (int64_t i = 0; i < nu; ++i) {
+    double s = 0.0;
+    for (int64_t k = L.K.rp[i]; k < L.K.rp[i + 1]; ++k) {
+      s += std::fabs(L.K.v[k]);
+      if (L.K.ci[k] == i) dg[i] = L.K.v[k];
+    }
+    at[i] = s;
+  }
+  L.atilde_inv.resize((size_t)nu);
+  L.jac_inv.resize((size_t)nu);
+  for (int64_t i = 0; i < nu; ++i) {
+    if (dg[i] == 0.0) fail(kErrZeroDiag, "zero diagonal entry in K");
+    double a = opt.atilde == 0 ? at[i] : dg[i];
+    if (a == 0.0) fail(kErrZeroDiag, "zero SIMPLEC lumping");
+    L.atilde_inv[i] = 1.0 / a;
+    L.jac_inv[i] = opt.jacobi_diag == 0 ? 1.0 / a : 1.0 / dg[i];
+  }
+  // S_d[j] = sum_i B[j,i] G[i,j] / Atilde_i - C[j,j]
+  L.sd_inv.resize((size_t)nl);
+  for (int64_t j = 0; j < nl; ++j) {
+    double s = 0.0;
+    for (int64_t k = L.B.rp[j]; k < L.B.rp[j + 1]; ++k) {
+      int32_t i = L.B.ci[k];
+      auto b = L.G.ci.begin() + L.G.rp[i], e = L.G.ci.begin() + L.G.rp[i + 1];
+      auto it = std::lower_bound(b, e, (int32_t)j);
+      if (it != e && *it == j) s += L.B.v[k] * L.G.v[it - L.G.ci.begin()] * L.atilde_inv[i];
+    }
+    double c = 0.0;
+    {
+      auto b = L.C.ci.begin() + L.C.rp[j], e = L.C.ci.begin() + L.C.rp[j + 1];
+      auto it = std::lower_bound(b, e, (int32_t)j);
+      if (it != e && *it == j) c = L.C.v[it - L.C.ci.begin()];
+    }
+    double sd = s - c;
+    if (sd == 0.0) fail(kErrZeroDiag, "zero diagonal of the Schur approximation");
+    L.sd_inv[j] = 1.0 / sd;
+  }
+}
+
+// Dense LU with partial pivoting (largest magnitude, first index on ties)
+// of the merged coarsest matrix, then its explicit inverse.
+void coarse_inverse(HostLevel& L) {
+  const int64_t nu = L.n_u(), n = L.n();
+  std::vector<double> A((size_t)(n * n), 0.0);
+  auto put = [&](const HostCSR& M, int64_t r0, int64_t c0) {
+    for (int64_t i = 0; i < M.nrows; ++i)
+      for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) A[(size_t)((r0 + i) * n + c0 + M.ci[k])] += M.v[k];
+  };
+  put(L.K, 0, 0);
+  put(L.G, 0, nu);
+  put(L.B, nu, 0);
+  put(L.C, nu, nu);
+  double amax = 0.0;
+  for (double a : A) amax = std::max(amax, std::fabs(a));
+  std::vector<int64_t> piv((size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t p = k;
+    double best = std::fabs(A[(size_t)(k * n + k)]);
+    for (int64_t i = k + 1; i < n; ++i) {
+      double v = std::fabs(A[(size_t)(i * n + k)]);
+      if (v > best) {
+        best = v;
+        p = i;
+      }
+    }
+    if (!(best > 1e-13 * amax)) fail(kErrSingularCoarse, "coarsest merged matrix is singular");
+    piv[k] = p;
+    if (p != k)
+      for (int64_t j = 0; j < n; ++j) std::swap(A[(size_t)(k * n + j)], A[(size_t)(p * n + j)]);
+    const double d = A[(size_t)(k * n + k)];
+    for (int64_t i = k + 1; i < n; ++i) {
+      double l = A[(size_t)(i * n + k)] / d;
+      A[(size_t)(i * n + k)] = l;
+      if (l != 0.0)
+        for (int64_t j = k + 1; j < n; ++j) A[(size_t)(i * n + j)] -= l * A[(size_t)(k * n + j)];
+    }
+  }
+  // inverse: solve A X = I column by column (row-major X)
+  L.Ainv.assign((size_t)(n * n), 0.0);
+  std::vector<double> x((size_t)n);
+  for (int64_t c = 0; c < n; ++c) {
+    std::fill(x.begin(), x.end(), 0.0);
+    x[c] = 1.0;
+    for (int64_t k = 0; k < n; ++k) std::swap(x[k], x[piv[k]]);
+    for (int64_t i = 0; i < n; ++i) {
+      double s = x[i];
+      for (int64_t j = 0; j < i; ++j) s -= A[(size_t)(i * n + j)] * x[j];
+      x[i] = s;
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double s = x[i];
+      for (int64_t j = i + 1; j < n; ++j) s -= A[(size_t)(i * n + j)] * x[j];
+      x[i] = s / A[(size_t)(i * n + i)];
+    }
+    for (int64_t i = 0; i < n; ++i) L.Ainv[(size_t)(i * n + c)] = x[i];
+  }
+}
+
+HostLevel coarsen(HostLevel& L) {
+  const int bs = L.bs_u;
+  const int64_t nn = L.n_u() / bs;
+  L.dirichlet = find_dirichlet(L.K, L.G);
+  std::vector<uint8_t> active((size_t)nn, 0);
+  for (int64_t a = 0; a < nn; ++a)
+    for (int c = 0; c < bs; ++c)
+      if (!L.dirichlet[a * bs + c]) active[a] = 1;
+  std::vector<int64_t> gp;
+  std::vector<int32_t> gi;
+  node_graph(L, gp, gi);
+  L.n_agg_u = aggregate_nodes(gp, gi, active, L.agg_u);
+  L.n_agg_l = lagmult_aggregation(L, L.agg_l);
+
+  HostLevel Cn;
+  std::vector<double> nsc_u, nsc_l;
+  tentative(
+      L.n_u(), L.n_ns_u, L.ns_u, L.agg_u, L.n_agg_u, [&](int64_t r) { return r / bs; },
+      [&](int64_t r) { return L.dirichlet[r] != 0; }, L.P_u, nsc_u);
+  tentative(
+      L.n_l(), L.n_ns_l, L.ns_l, L.agg_l, L.n_agg_l, [&](int64_t r) { return (int64_t)L.lm_node[r]; },
+      [&](int64_t) { return false; }, L.P_l, nsc_l);
+  HostCSR Ru = transpose(L.P_u), Rl = transpose(L.P_l);
+  Cn.K = galerkin(Ru, L.K, L.P_u);
+  Cn.G = galerkin(Ru, L.G, L.P_l);
+  Cn.B = galerkin(Rl, L.B, L.P_u);
+  Cn.C = galerkin(Rl, L.C, L.P_l);
+  Cn.bs_u = L.n_ns_u;
+  Cn.bs_l = L.n_ns_l;
+  Cn.n_ns_u = L.n_ns_u;
+  Cn.n_ns_l = L.n_ns_l;
+  Cn.slave_node.assign((size_t)L.n_agg_u, 0);
+  Cn.master_node.assign((size_t)L.n_agg_u, 0);
+  for (int64_t a = 0; a < nn; ++a) {
+    int32_t g = L.agg_u[a];
+    if (g < 0) continue;
+    if (L.slave_node[a]) Cn.slave_node[g] = 1;
+    if (L.master_node[a]) Cn.master_node[g] = 1;
+  }
+  Cn.n_nodes_l = L.n_agg_l;
+  Cn.lm_node.resize((size_t)(L.n_agg_l * L.n_ns_l));
+  for (size_t j = 0; j < Cn.lm_node.size(); ++j) Cn.lm_node[j] = (int32_t)(j / L.n_ns_l);
+  Cn.ns_u = std::move(nsc_u);
+  Cn.ns_l = std::move(nsc_l);
+  return Cn;
+}
+
+}  // namespace
+
+HostCSR transpose(const HostCSR& A, std::vector<int32_t>* perm) {
+  HostCSR T;
+  T.init_empty(A.ncols, A.nrows);
+  for (int32_t c : A.ci) T.rp[c + 1]++;
+  for (int64_t i = 0; i < A.ncols; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(A.ci.size());
+  T.v.resize(A.ci.size());
+  if (perm) perm->resize(A.ci.size());
+  std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int64_t i = 0; i < A.nrows; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      int64_t p = pos[A.ci[k]]++;
+      T.ci[p] = (int32_t)i;
+      T.v[p] = A.v[k];
+      if (perm) (*perm)[k] = (int32_t)p;
+    }
+  return T;
+}
+
+void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt) {
+  while ((int)levels.size() < opt.max_levels && levels.back().n() > opt.max_coarse_rows) {
+    HostLevel nxt = coarsen(levels.back());
+    if (nxt.n() >= levels.back().n()) {
+      // no coarsening progress: drop the aggregation data of the last level
+      HostLevel& L = levels.back();
+      L.agg_u.clear();
+      L.agg_l.clear();
+      L.n_agg_u = L.n_agg_l = 0;
+      L.P_u = HostCSR();
+      L.P_l = HostCSR();
+      break;
+    }
+    levels.push_back(std::move(nxt));
+  }
+  for (size_t l = 0; l + 1 < levels.size(); ++l) smoother_data(levels[l], opt);
+  coarse_inverse(levels.back());
+}
+
+}  // namespace camg

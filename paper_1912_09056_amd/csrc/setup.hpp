@@ -1,0 +1,72 @@
+// Host-side construction of the fully coupled aggregation-AMG hierarchy.
+//
+// Runs once per amg_setup (outside the timed solve).  Integer work
+// (aggregation, multiplier aggregation) is inherently sequential greedy
+// graph work; the numeric products are row-parallel-friendly but small
+// next to the solve, so both stay on the host here and the results are
+// uploaded.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace camg {
+
+struct HostCSR {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> rp;  // nrows + 1
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  int64_t nnz() const { return (int64_t)ci.size(); }
+  void init_empty(int64_t r, int64_t c) {
+    nrows = r;
+    ncols = c;
+    rp.assign((size_t)r + 1, 0);
+    ci.clear();
+    v.clear();
+  }
+};
+
+struct HostLevel {
+  HostCSR K, G, B, C;
+  int bs_u = 0, bs_l = 0;          // dofs per displacement node / multiplier node
+  int n_ns_u = 0, n_ns_l = 0;      // null-space columns (next level's block sizes)
+  std::vector<uint8_t> slave_node, master_node;  // per displacement node
+  std::vector<int32_t> lm_node;    // multiplier dof -> pseudo-node
+  int64_t n_nodes_l = 0;
+  std::vector<double> ns_u, ns_l;  // column-major null spaces
+  std::vector<uint8_t> dirichlet;  // per displacement dof
+  std::vector<int32_t> agg_u, agg_l;
+  int64_t n_agg_u = 0, n_agg_l = 0;
+  HostCSR P_u, P_l;
+  std::vector<double> atilde_inv, jac_inv, sd_inv;
+  std::vector<double> Ainv;        // coarsest level: dense inverse, row-major
+  int64_t n_u() const { return K.nrows; }
+  int64_t n_l() const { return C.nrows; }
+  int64_t n() const { return n_u() + n_l(); }
+  int64_t nnz_all() const { return K.nnz() + G.nnz() + B.nnz() + C.nnz(); }
+};
+
+struct SetupOptions {
+  int max_levels = 4;
+  int max_coarse_rows = 1000;
+  int atilde = 0;       // 0 row sums of |K|, 1 diag(K)
+  int jacobi_diag = 0;  // 0 Atilde, 1 diag(K)
+};
+
+// Status codes mirror the C-ABI's CAMG_* values.
+struct SetupError {
+  int code;
+  std::string msg;
+};
+
+// Transpose keeping explicit zeros; rows of the result are sorted.
+// If perm is given, perm[k] = position of input entry k in the output.
+HostCSR transpose(const HostCSR& A, std::vector<int32_t>* perm = nullptr);
+
+// Builds all levels.  levels[0] must hold K, G, B, C, bs_u/bs_l, n_ns_*,
+// node masks, lm_node, n_nodes_l and the level-0 null spaces.
+void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt);
+
+}  // namespace camg

@@ -1,0 +1,891 @@
+// libcamg: C-ABI, device hierarchy, V-cycle and FGMRES orchestration.
+//
+// Host code here only sequences kernels; every vector operation of the
+// solve phase runs on the GPU.  The only per-iteration device-to-host
+// traffic is the Hessenberg residual estimate (and the Arnoldi norm) read
+// every `check_every` iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/camg.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+namespace camg {
+
+thread_local std::string g_last_error;
+
+struct ApiError {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] static void api_fail(int code, const std::string& m) { throw ApiError{code, m}; }
+
+// ---------------------------------------------------------------------------
+// device matrices
+
+struct DevMat {
+  int32_t nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  DBuf<int32_t> rp, ci;
+  DBuf<double> v64;
+  DBuf<float> v32;
+  template <typename T>
+  DCSR<T> view() const;
+};
+
+template <>
+DCSR<double> DevMat::view<double>() const {
+  DCSR<double> d;
+  d.nrows = nrows;
+  d.ncols = ncols;
+  d.nnz = nnz;
+  d.rp = rp.p;
+  d.ci = ci.p;
+  d.v = v64.p;
+  return d;
+}
+template <>
+DCSR<float> DevMat::view<float>() const {
+  DCSR<float> d;
+  d.nrows = nrows;
+  d.ncols = ncols;
+  d.nnz = nnz;
+  d.rp = rp.p;
+  d.ci = ci.p;
+  d.v = v32.p;
+  return d;
+}
+
+static void upload_mat(DevMat& D, const HostCSR& H, bool f64, bool f32, hipStream_t s) {
+  D.nrows = (int32_t)H.nrows;
+  D.ncols = (int32_t)H.ncols;
+  D.nnz = H.nnz();
+  std::vector<int32_t> rp32(H.rp.size());
+  for (size_t i = 0; i < H.rp.size(); ++i) rp32[i] = (int32_t)H.rp[i];
+  D.rp.upload(rp32, s);
+  D.ci.upload(H.ci, s);
+  if (f64) D.v64.upload(H.v, s);
+  if (f32) {
+    std::vector<float> v32(H.v.size());
+    for (size_t i = 0; i < H.v.size(); ++i) v32[i] = (float)H.v[i];
+    D.v32.upload(v32, s);
+  }
+  CAMG_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
+}
+
+template <typename T>
+struct LevelVecs {
+  DBuf<T> b, z, zn, r, delta, aux1, aux2, su;
+  DBuf<T> jinv, ainv, sdinv;
+  DBuf<T> Ainv, AinvT;
+};
+
+struct DevLevel {
+  int64_t n_u = 0, n_l = 0;
+  DevMat K, G, B, C, KT, GT, BT, CT, Pu, Pl, Ru, Rl;
+  DBuf<int32_t> g_rows;
+  int32_t n_g_rows = 0;
+  int sg_K = 16, sg_R = 16, sg_P = 8;
+  LevelVecs<double> v64;
+  LevelVecs<float> v32;
+  int64_t n() const { return n_u + n_l; }
+};
+
+// ---------------------------------------------------------------------------
+// profiling (hipEvents around launches of selected kernel classes)
+
+struct Prof {
+  int mask = 0;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  hipEvent_t get() {
+    if (pool_used == pool.size()) {
+      hipEvent_t e;
+      CAMG_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[pool_used++];
+  }
+  ~Prof() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct ProfScope {
+  Prof* p;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(Prof* prof, int c, hipStream_t st) : p(prof), cls(c), s(st) {
+    if (p && (p->mask & cls)) {
+      a = p->get();
+      CAMG_HIP(hipEventRecord(a, s));
+    }
+  }
+  ~ProfScope() noexcept(false) {
+    if (a) {
+      hipEvent_t b = p->get();
+      CAMG_HIP(hipEventRecord(b, s));
+      p->recs.push_back({cls, a, b});
+    }
+  }
+};
+
+}  // namespace camg
+
+using namespace camg;
+
+struct amg_handle {
+  int device = 0;
+  amg_options opts{};
+  int dim = 0;
+  std::vector<HostLevel> host;
+  std::vector<DevLevel> lev;
+  std::vector<int32_t> perm_K, perm_G, perm_B, perm_C;
+  DBuf<int32_t> d_perm_K, d_perm_G, d_perm_B, d_perm_C;
+  int64_t n = 0, n_u = 0, n_l = 0;
+  // Krylov workspace
+  int m_alloc = 0;
+  DBuf<double> V, Z, w, r, H, cs, sn, g, h1, h2, hn2, partial, out, y;
+  double* hbuf = nullptr;  // pinned host mirror of `out`
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  Prof prof;
+  ~amg_handle() {
+    if (hbuf) (void)hipHostFree(hbuf);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace camg {
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+static void check_csr(const amg_csr& A, int64_t nrows, int64_t ncols, const char* name) {
+  const std::string nm(name);
+  if (A.nrows != nrows || A.ncols != ncols) api_fail(CAMG_ERR_SHAPE, nm + ": wrong dimensions");
+  if (A.nnz < 0 || A.nnz >= (int64_t(1) << 31)) api_fail(CAMG_ERR_SHAPE, nm + ": nnz out of range");
+  if (nrows > 0 && !A.rowptr) api_fail(CAMG_ERR_INVALID_ARG, nm + ": rowptr is NULL");
+  if (A.nnz > 0 && (!A.col || !A.val)) api_fail(CAMG_ERR_INVALID_ARG, nm + ": col/val is NULL");
+  if (nrows == 0) return;
+  if (A.rowptr[0] != 0 || A.rowptr[nrows] != A.nnz) api_fail(CAMG_ERR_SHAPE, nm + ": rowptr ends do not match nnz");
+  for (int64_t i = 0; i < nrows; ++i) {
+    if (A.rowptr[i + 1] < A.rowptr[i]) api_fail(CAMG_ERR_SHAPE, nm + ": rowptr not monotone");
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+      if (A.col[k] < 0 || A.col[k] >= ncols) api_fail(CAMG_ERR_SHAPE, nm + ": column index out of range");
+      if (k > A.rowptr[i] && A.col[k] <= A.col[k - 1]) api_fail(CAMG_ERR_SHAPE, nm + ": columns not sorted/unique");
+      if (!std::isfinite(A.val[k])) api_fail(CAMG_ERR_NONFINITE, nm + ": non-finite value");
+    }
+  }
+}
+
+static HostCSR to_host(const amg_csr& A) {
+  HostCSR H;
+  H.nrows = A.nrows;
+  H.ncols = A.ncols;
+  H.rp.assign(A.rowptr, A.rowptr + A.nrows + 1);
+  if (A.nnz) {
+    H.ci.assign(A.col, A.col + A.nnz);
+    H.v.assign(A.val, A.val + A.nnz);
+  }
+  return H;
+}
+
+template <typename T>
+static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool coarsest, hipStream_t s) {
+  const int64_t n = H.n(), nu = H.n_u(), nl = H.n_l();
+  for (DBuf<T>* b : {&V.b, &V.z, &V.zn, &V.r}) {
+    b->alloc((size_t)n);
+    zero_vec<T>(b->p, n, s);
+  }
+  V.delta.alloc((size_t)std::max<int64_t>(nl, 1));
+  zero_vec<T>(V.delta.p, std::max<int64_t>(nl, 1), s);
+  for (DBuf<T>* b : {&V.aux1, &V.aux2, &V.su}) {
+    b->alloc((size_t)std::max<int64_t>(nu, 1));
+    zero_vec<T>(b->p, std::max<int64_t>(nu, 1), s);
+  }
+  auto up = [&](DBuf<T>& d, const std::vector<double>& h) {
+    std::vector<T> t(h.begin(), h.end());
+    d.upload(t, s);
+    CAMG_HIP(hipStreamSynchronize(s));
+  };
+  if (!coarsest) {
+    up(V.jinv, H.jac_inv);
+    up(V.ainv, H.atilde_inv);
+    up(V.sdinv, H.sd_inv);
+  } else {
+    up(V.Ainv, H.Ainv);
+    std::vector<double> t(H.Ainv.size());
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < n; ++j) t[(size_t)(j * n + i)] = H.Ainv[(size_t)(i * n + j)];
+    up(V.AinvT, t);
+  }
+}
+
+static void upload_hierarchy(amg_handle& h, hipStream_t s) {
+  const bool mixed = h.opts.precision == CAMG_PREC_MIXED;
+  const size_t L = h.host.size();
+  h.lev.resize(L);
+  for (size_t l = 0; l < L; ++l) {
+    HostLevel& H = h.host[l];
+    DevLevel& D = h.lev[l];
+    const bool coarsest = (l + 1 == L);
+    const bool f64 = !mixed || l == 0;  // level 0 in FP64 always (outer operator)
+    const bool f32 = mixed;
+    D.n_u = H.n_u();
+    D.n_l = H.n_l();
+    upload_mat(D.K, H.K, f64, f32, s);
+    upload_mat(D.G, H.G, f64, f32, s);
+    upload_mat(D.B, H.B, f64, f32, s);
+    upload_mat(D.C, H.C, f64, f32, s);
+    std::vector<int32_t>* perms[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (l == 0) perms[0] = &h.perm_K, perms[1] = &h.perm_G, perms[2] = &h.perm_B, perms[3] = &h.perm_C;
+    upload_mat(D.KT, transpose(H.K, perms[0]), f64, f32, s);
+    upload_mat(D.GT, transpose(H.G, perms[1]), f64, f32, s);
+    upload_mat(D.BT, transpose(H.B, perms[2]), f64, f32, s);
+    upload_mat(D.CT, transpose(H.C, perms[3]), f64, f32, s);
+    D.sg_K = pick_subgroup(H.K.nnz(), H.K.nrows);
+    if (!coarsest) {
+      const bool t64 = !mixed;
+      upload_mat(D.Pu, H.P_u, t64, f32, s);
+      upload_mat(D.Pl, H.P_l, t64, f32, s);
+      HostCSR Ru = transpose(H.P_u), Rl = transpose(H.P_l);
+      upload_mat(D.Ru, Ru, t64, f32, s);
+      upload_mat(D.Rl, Rl, t64, f32, s);
+      D.sg_R = pick_subgroup(Ru.nnz(), Ru.nrows);
+      D.sg_P = pick_subgroup(H.P_u.nnz(), H.P_u.nrows);
+      std::vector<int32_t> gr;
+      for (int64_t i = 0; i < H.G.nrows; ++i)
+        if (H.G.rp[i + 1] > H.G.rp[i]) gr.push_back((int32_t)i);
+      D.n_g_rows = (int32_t)gr.size();
+      D.g_rows.upload(gr, s);
+    }
+    if (mixed) alloc_vecs<float>(D.v32, H, coarsest, s);
+    else alloc_vecs<double>(D.v64, H, coarsest, s);
+    if (mixed && l == 0) {
+      // FP64 level-0 vectors for operator applies outside the V-cycle
+      D.v64.r.alloc((size_t)H.n());
+    }
+  }
+  h.d_perm_K.upload(h.perm_K, s);
+  h.d_perm_G.upload(h.perm_G, s);
+  h.d_perm_B.upload(h.perm_B, s);
+  h.d_perm_C.upload(h.perm_C, s);
+  CAMG_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+
+template <typename T>
+static LevelVecs<T>& vecs(DevLevel& D);
+template <>
+LevelVecs<double>& vecs<double>(DevLevel& D) {
+  return D.v64;
+}
+template <>
+LevelVecs<float>& vecs<float>(DevLevel& D) {
+  return D.v32;
+}
+
+template <typename T>
+static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, T* zn, bool first, hipStream_t s) {
+  DevLevel& D = h.lev[l];
+  LevelVecs<T>& V = vecs<T>(D);
+  const int nu = (int)D.n_u, nl = (int)D.n_l;
+  const T om = (T)h.opts.jacobi_omega, al = (T)h.opts.simple_alpha;
+  const int nj = std::max(1, h.opts.jacobi_sweeps);
+  const T* bu = b;
+  const T* bl = b + nu;
+  const T* zu = z;
+  const T* zl = z + nu;
+  T* znu = zn;
+  T* znl = zn + nu;
+  Prof* pp = (l == 0) ? &h.prof : nullptr;
+  if (!transpose) {
+    {
+      ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
+      smooth_u<T>(D.K.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, nj > 1 ? V.aux1.p : nullptr,
+                  nj > 1 ? V.aux2.p : nullptr, nu, first, D.sg_K, s);
+    }
+    T* wa = V.aux2.p;
+    T* wb = V.su.p;
+    for (int k = 1; k < nj; ++k) {
+      jacobi_extra<T>(D.K.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
+                      D.sg_K, s);
+      std::swap(wa, wb);
+    }
+    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, V.sdinv.p, al, znl, V.delta.p, nl, first, s);
+    correct_u<T>(D.G.view<T>(), D.g_rows.p, D.n_g_rows, V.delta.p, V.ainv.p, al, znu, s);
+  } else {
+    {
+      ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
+      tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, first, D.sg_K, s);
+    }
+    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, V.su.p, V.ainv.p, V.sdinv.p, al, znl, V.delta.p, nl,
+                 first, s);
+    tcorrect_u<T>(D.BT.view<T>(), V.su.p, V.delta.p, V.jinv.p, om, al, zu, znu, nj > 1 ? V.aux1.p : nullptr,
+                  nj > 1 ? V.aux2.p : nullptr, nu, first, s);
+    T* wa = V.aux2.p;
+    T* wb = V.r.p;  // r is free during a sweep
+    for (int k = 1; k < nj; ++k) {
+      jacobi_extra<T>(D.KT.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
+                      D.sg_K, s);
+      std::swap(wa, wb);
+    }
+  }
+}
+
+// Runs the cycle from level l on vecs(l).b; returns the buffer holding z.
+template <typename T>
+static T* vcycle_level(amg_handle& h, int l, bool transpose, hipStream_t s) {
+  DevLevel& D = h.lev[l];
+  LevelVecs<T>& V = vecs<T>(D);
+  const int nu = (int)D.n_u, nl = (int)D.n_l;
+  const int last = (int)h.lev.size() - 1;
+  if (l == last) {
+    dense_gemv<T>(transpose ? V.AinvT.p : V.Ainv.p, V.b.p, V.z.p, (int)D.n(), s);
+    return V.z.p;
+  }
+  const int npre = transpose ? h.opts.nu_post : h.opts.nu_pre;
+  const int npost = transpose ? h.opts.nu_pre : h.opts.nu_post;
+  T* zc = V.z.p;
+  T* zx = V.zn.p;
+  bool first = true;
+  for (int k = 0; k < npre; ++k) {
+    sweep<T>(h, l, transpose, V.b.p, zc, zx, first, s);
+    std::swap(zc, zx);
+    first = false;
+  }
+  if (first) zero_vec<T>(zc, D.n(), s);
+  {
+    ProfScope ps(l == 0 ? &h.prof : nullptr, CAMG_KCLASS_RESIDUAL, s);
+    if (!transpose)
+      blk_spmv<T>(D.K.view<T>(), D.G.view<T>(), D.B.view<T>(), D.C.view<T>(), zc, zc + nu, V.b.p, V.b.p + nu, V.r.p,
+                  V.r.p + nu, nu, nl, 1, D.sg_K, s);
+    else
+      blk_spmv<T>(D.KT.view<T>(), D.BT.view<T>(), D.GT.view<T>(), D.CT.view<T>(), zc, zc + nu, V.b.p, V.b.p + nu,
+                  V.r.p, V.r.p + nu, nu, nl, 1, D.sg_K, s);
+  }
+  DevLevel& Dc = h.lev[l + 1];
+  LevelVecs<T>& Vc = vecs<T>(Dc);
+  const int ncu = (int)Dc.n_u, ncl = (int)Dc.n_l;
+  DCSR<T> none;
+  blk_spmv<T>(D.Ru.view<T>(), none, none, D.Rl.view<T>(), V.r.p, V.r.p + nu, nullptr, nullptr, Vc.b.p, Vc.b.p + ncu,
+              ncu, ncl, 0, D.sg_R, s);
+  T* zcoarse = vcycle_level<T>(h, l + 1, transpose, s);
+  blk_spmv<T>(D.Pu.view<T>(), none, none, D.Pl.view<T>(), zcoarse, zcoarse + ncu, nullptr, nullptr, zc, zc + nu, nu,
+              nl, 2, D.sg_P, s);
+  for (int k = 0; k < npost; ++k) {
+    sweep<T>(h, l, transpose, V.b.p, zc, zx, false, s);
+    std::swap(zc, zx);
+  }
+  return zc;
+}
+
+// z = M^{-1} r (or M^{-T} r) on FP64 device vectors.
+static void precondition(amg_handle& h, bool transpose, const double* r, double* z, hipStream_t s) {
+  DevLevel& D0 = h.lev[0];
+  const int64_t n = D0.n();
+  if (h.opts.precision == CAMG_PREC_MIXED) {
+    cast_d2f(r, D0.v32.b.p, n, s);
+    float* out = vcycle_level<float>(h, 0, transpose, s);
+    cast_f2d(out, z, n, s);
+  } else {
+    copy_vec<double>(r, D0.v64.b.p, n, s);
+    double* out = vcycle_level<double>(h, 0, transpose, s);
+    copy_vec<double>(out, z, n, s);
+  }
+}
+
+// y = A x, or y = b - A x when b is given (FP64 level-0 operator).
+static void apply_op(amg_handle& h, bool transpose, const double* x, const double* b, double* y, hipStream_t s) {
+  DevLevel& D = h.lev[0];
+  const int nu = (int)D.n_u, nl = (int)D.n_l;
+  ProfScope ps(&h.prof, CAMG_KCLASS_OPERATOR, s);
+  const int mode = b ? 1 : 0;
+  if (!transpose)
+    blk_spmv<double>(D.K.view<double>(), D.G.view<double>(), D.B.view<double>(), D.C.view<double>(), x, x + nu, b,
+                     b ? b + nu : nullptr, y, y + nu, nu, nl, mode, D.sg_K, s);
+  else
+    blk_spmv<double>(D.KT.view<double>(), D.BT.view<double>(), D.GT.view<double>(), D.CT.view<double>(), x, x + nu, b,
+                     b ? b + nu : nullptr, y, y + nu, nu, nl, mode, D.sg_K, s);
+}
+
+static void ensure_krylov(amg_handle& h, int m) {
+  if (h.m_alloc >= m) return;
+  const int64_t n = h.n;
+  h.V.alloc((size_t)(n * (m + 1)));
+  h.Z.alloc((size_t)(n * m));
+  h.w.alloc((size_t)n);
+  h.r.alloc((size_t)n);
+  h.H.alloc((size_t)((m + 1) * m));
+  h.cs.alloc((size_t)m);
+  h.sn.alloc((size_t)m);
+  h.g.alloc((size_t)(m + 1));
+  h.h1.alloc((size_t)(m + 1));
+  h.h2.alloc((size_t)(m + 1));
+  h.hn2.alloc(1);
+  h.partial.alloc((size_t)((m + 1) * mdot_blocks(n)));
+  h.out.alloc(4);
+  h.y.alloc((size_t)m);
+  h.m_alloc = m;
+}
+
+static void read_out(amg_handle& h, hipStream_t s) {
+  CAMG_HIP(hipMemcpyAsync(h.hbuf, h.out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  CAMG_HIP(hipStreamSynchronize(s));
+}
+
+static int gmres(amg_handle& h, bool transpose, const double* b, double* x, const amg_gmres_options& o,
+                 amg_gmres_result* res, hipStream_t s) {
+  const int m = o.m;
+  const int64_t n = h.n;
+  ensure_krylov(h, m);
+  const bool fixed = o.fixed_iters > 0;
+  const int limit = fixed ? o.fixed_iters : o.max_iters;
+  const int check = std::max(1, o.check_every);
+  CAMG_HIP(hipEventRecord(h.ev0, s));
+  // r0 = b - A x0, beta = ||r0||
+  apply_op(h, transpose, x, b, h.r.p, s);
+  mdot(h.r.p, n, 1, h.r.p, n, h.partial.p, h.hn2.p, s);
+  restart_init(h.r.p, h.hn2.p, h.V.p, h.g.p, m + 1, h.out.p, n, s);
+  read_out(h, s);
+  const double r0 = h.hbuf[0];
+  if (!std::isfinite(r0)) api_fail(CAMG_ERR_NONFINITE, "non-finite initial residual");
+  int total = 0, restarts = 0;
+  double est = 1.0, true_rel = 1.0;
+  int status = CAMG_NOT_CONVERGED;
+  if (r0 == 0.0) {
+    est = true_rel = 0.0;
+    status = CAMG_OK;
+  } else {
+    for (;;) {
+      int k = 0;
+      bool stop_inner = false;
+      for (int j = 0; j < m && !stop_inner; ++j) {
+        double* vj = h.V.p + (int64_t)j * n;
+        double* zj = h.Z.p + (int64_t)j * n;
+        precondition(h, transpose, vj, zj, s);
+        apply_op(h, transpose, zj, nullptr, h.w.p, s);
+        {
+          ProfScope ps(&h.prof, CAMG_KCLASS_ORTHO, s);
+          mdot(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h1.p, s);
+          gemv_acc(h.V.p, n, j + 1, h.h1.p, -1.0, h.w.p, n, s);
+          mdot(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h2.p, s);
+          gemv_acc(h.V.p, n, j + 1, h.h2.p, -1.0, h.w.p, n, s);
+          mdot(h.w.p, n, 1, h.w.p, n, h.partial.p, h.hn2.p, s);
+        }
+        arnoldi_update(h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p, h.h1.p, h.h2.p, h.hn2.p, j, h.out.p, s);
+        scale_by(h.w.p, h.out.p + 2, h.V.p + (int64_t)(j + 1) * n, n, s);
+        ++total;
+        k = j + 1;
+        const bool at_check = (total % check == 0) || (j == m - 1) || (total >= limit);
+        if (at_check) {
+          read_out(h, s);
+          est = h.hbuf[0] / r0;
+          if (!std::isfinite(est)) api_fail(CAMG_ERR_NONFINITE, "non-finite residual estimate");
+          if (h.hbuf[1] == 0.0) stop_inner = true;           // happy breakdown
+          if (!fixed && est <= o.rtol) stop_inner = true;
+        }
+        if (total >= limit) stop_inner = true;
+      }
+      hess_solve(h.H.p, m + 1, h.g.p, h.y.p, k, s);
+      gemv_acc(h.Z.p, n, k, h.y.p, 1.0, x, n, s);
+      apply_op(h, transpose, x, b, h.r.p, s);
+      mdot(h.r.p, n, 1, h.r.p, n, h.partial.p, h.hn2.p, s);
+      restart_init(h.r.p, h.hn2.p, h.V.p, h.g.p, m + 1, h.out.p, n, s);
+      read_out(h, s);
+      true_rel = h.hbuf[0] / r0;
+      if (!std::isfinite(true_rel)) api_fail(CAMG_ERR_NONFINITE, "non-finite residual");
+      if (fixed) {
+        if (total >= limit) {
+          status = CAMG_OK;
+          break;
+        }
+      } else {
+        if (true_rel <= o.rtol) {
+          status = CAMG_OK;
+          break;
+        }
+        if (total >= limit) break;
+      }
+      if (h.hbuf[0] == 0.0) {
+        status = CAMG_OK;
+        break;
+      }
+      ++restarts;
+    }
+  }
+  CAMG_HIP(hipEventRecord(h.ev1, s));
+  CAMG_HIP(hipEventSynchronize(h.ev1));
+  float ms = 0.f;
+  CAMG_HIP(hipEventElapsedTime(&ms, h.ev0, h.ev1));
+  if (res) {
+    res->iters = total;
+    res->restarts = restarts;
+    res->status = status;
+    res->rel_res_est = est;
+    res->rel_res_true = true_rel;
+    res->seconds = ms * 1e-3;
+  }
+  return status;
+}
+
+template <typename F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const ApiError& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const SetupError& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const HipError& e) {
+    g_last_error = std::string("HIP error ") + hipGetErrorString(e.err) + " in " + e.where;
+    return CAMG_ERR_HIP;
+  } catch (const OomError& e) {
+    g_last_error = "device allocation of " + std::to_string(e.bytes) + " bytes failed";
+    return CAMG_ERR_OOM;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return CAMG_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CAMG_ERR_INVALID_ARG;
+  }
+}
+
+}  // namespace camg
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+void amg_default_options(amg_options* o) {
+  if (!o) return;
+  o->max_levels = 4;
+  o->max_coarse_rows = 1000;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->jacobi_sweeps = 1;
+  o->atilde = CAMG_ATILDE_ROWSUM_ABS;
+  o->jacobi_diag = CAMG_JACOBI_ATILDE;
+  o->precision = CAMG_PREC_FP64;
+  o->jacobi_omega = 0.8;
+  o->simple_alpha = 0.8;
+}
+
+void amg_default_gmres_options(amg_gmres_options* o) {
+  if (!o) return;
+  o->m = 50;
+  o->max_iters = 1000;
+  o->fixed_iters = 0;
+  o->check_every = 1;
+  o->rtol = 1e-8;
+}
+
+}  // extern "C"
+
+namespace camg {
+
+static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_options* opts) {
+  if (!p) api_fail(CAMG_ERR_INVALID_ARG, "NULL problem");
+  amg_options o;
+  amg_default_options(&o);
+  if (opts) o = *opts;
+  if (p->dim < 1 || p->dim > 3) api_fail(CAMG_ERR_INVALID_ARG, "dim must be 1..3");
+  if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
+      (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 1 ||
+      o.jacobi_diag < 0 || o.jacobi_diag > 1)
+    api_fail(CAMG_ERR_INVALID_ARG, "invalid options");
+  const int64_t nu = p->K.nrows, nl = p->C.nrows;
+  if (nu <= 0 || nu % p->dim) api_fail(CAMG_ERR_SHAPE, "n_u must be a positive multiple of dim");
+  if (nl < 0 || nu + nl >= (int64_t(1) << 31)) api_fail(CAMG_ERR_SHAPE, "system too large");
+  check_csr(p->K, nu, nu, "K");
+  check_csr(p->G, nu, nl, "G");
+  check_csr(p->B, nl, nu, "B");
+  check_csr(p->C, nl, nl, "C");
+  if ((p->n_slave > 0 && !p->slave_dofs) || (p->n_master > 0 && !p->master_dofs) || p->n_slave < 0 ||
+      p->n_master < 0)
+    api_fail(CAMG_ERR_INVALID_ARG, "interface dof lists");
+  auto h = std::make_unique<amg_handle>();
+  h->opts = o;
+  h->dim = p->dim;
+  h->n_u = nu;
+  h->n_l = nl;
+  h->n = nu + nl;
+
+  HostLevel L0;
+  L0.K = to_host(p->K);
+  L0.G = to_host(p->G);
+  L0.B = to_host(p->B);
+  L0.C = to_host(p->C);
+  L0.bs_u = p->dim;
+  L0.bs_l = p->dim;
+  const int64_t nn = nu / p->dim;
+  L0.slave_node.assign((size_t)nn, 0);
+  L0.master_node.assign((size_t)nn, 0);
+  for (int32_t i = 0; i < p->n_slave; ++i) {
+    if (p->slave_dofs[i] < 0 || p->slave_dofs[i] >= nu) api_fail(CAMG_ERR_SHAPE, "slave dof out of range");
+    L0.slave_node[p->slave_dofs[i] / p->dim] = 1;
+  }
+  for (int32_t i = 0; i < p->n_master; ++i) {
+    if (p->master_dofs[i] < 0 || p->master_dofs[i] >= nu) api_fail(CAMG_ERR_SHAPE, "master dof out of range");
+    L0.master_node[p->master_dofs[i] / p->dim] = 1;
+  }
+  L0.lm_node.resize((size_t)nl);
+  int64_t maxnode = -1;
+  for (int64_t j = 0; j < nl; ++j) {
+    int32_t v = p->lm_node ? p->lm_node[j] : (int32_t)(j / p->dim);
+    if (v < 0) api_fail(CAMG_ERR_SHAPE, "negative multiplier pseudo-node");
+    L0.lm_node[j] = v;
+    maxnode = std::max<int64_t>(maxnode, v);
+  }
+  L0.n_nodes_l = maxnode + 1;
+  if (p->nullspace && p->n_ns > 0) {
+    L0.n_ns_u = p->n_ns;
+    L0.ns_u.assign(p->nullspace, p->nullspace + (size_t)nu * p->n_ns);
+    for (double v : L0.ns_u)
+      if (!std::isfinite(v)) api_fail(CAMG_ERR_NONFINITE, "non-finite null space");
+  } else {
+    L0.n_ns_u = p->dim;
+    L0.ns_u.assign((size_t)nu * p->dim, 0.0);
+    for (int64_t i = 0; i < nu; ++i) L0.ns_u[(size_t)(i % p->dim) * nu + i] = 1.0;
+  }
+  L0.n_ns_l = p->dim;
+  L0.ns_l.assign((size_t)nl * p->dim, 0.0);
+  for (int64_t j = 0; j < nl; ++j) L0.ns_l[(size_t)(j % p->dim) * nl + j] = 1.0;
+  h->host.push_back(std::move(L0));
+
+  SetupOptions so;
+  so.max_levels = o.max_levels;
+  so.max_coarse_rows = o.max_coarse_rows;
+  so.atilde = o.atilde;
+  so.jacobi_diag = o.jacobi_diag;
+  build_hierarchy(h->host, so);
+  return h;
+}
+
+static void need_device(const amg_handle* h) {
+  if (h->lev.empty()) api_fail(CAMG_ERR_INVALID_ARG, "handle was built by amg_setup_host and has no device data");
+}
+
+}  // namespace camg
+
+extern "C" {
+
+int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_handle** out) {
+  return guarded([&]() -> int {
+    if (!out) api_fail(CAMG_ERR_INVALID_ARG, "NULL output handle");
+    *out = nullptr;
+    auto h = build_host(p, opts);
+    hipStream_t s = as_stream(stream);
+    CAMG_HIP(hipGetDevice(&h->device));
+    CAMG_HIP(hipEventCreate(&h->ev0));
+    CAMG_HIP(hipEventCreate(&h->ev1));
+    CAMG_HIP(hipHostMalloc((void**)&h->hbuf, 4 * sizeof(double), hipHostMallocDefault));
+    upload_hierarchy(*h, s);
+    *out = h.release();
+    return CAMG_OK;
+  });
+}
+
+int amg_setup_host(const amg_problem* p, const amg_options* opts, amg_handle** out) {
+  return guarded([&]() -> int {
+    if (!out) api_fail(CAMG_ERR_INVALID_ARG, "NULL output handle");
+    *out = nullptr;
+    *out = build_host(p, opts).release();
+    return CAMG_OK;
+  });
+}
+
+int amg_num_levels(const amg_handle* h) { return h ? (int)h->host.size() : CAMG_ERR_INVALID_ARG; }
+
+int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out) {
+  return guarded([&]() -> int {
+    if (!h || !out || level < 0 || level >= (int)h->host.size()) api_fail(CAMG_ERR_INVALID_ARG, "level");
+    const HostLevel& L = h->host[level];
+    out->n_u = L.n_u();
+    out->n_l = L.n_l();
+    out->nnz_K = L.K.nnz();
+    out->nnz_G = L.G.nnz();
+    out->nnz_B = L.B.nnz();
+    out->nnz_C = L.C.nnz();
+    out->bs_u = L.bs_u;
+    out->bs_l = L.bs_l;
+    out->n_nodes_u = L.n_u() / std::max(1, L.bs_u);
+    out->n_nodes_l = L.n_nodes_l;
+    out->n_agg_u = L.n_agg_u;
+    out->n_agg_l = L.n_agg_l;
+    double tot = 0.0;
+    for (const auto& X : h->host) tot += (double)X.nnz_all();
+    out->op_complexity = tot / (double)h->host[0].nnz_all();
+    return CAMG_OK;
+  });
+}
+
+int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_t* lm_agg) {
+  return guarded([&]() -> int {
+    if (!h || level < 0 || level + 1 >= (int)h->host.size()) api_fail(CAMG_ERR_INVALID_ARG, "level");
+    const HostLevel& L = h->host[level];
+    if (disp_agg) std::copy(L.agg_u.begin(), L.agg_u.end(), disp_agg);
+    if (lm_agg) std::copy(L.agg_l.begin(), L.agg_l.end(), lm_agg);
+    return CAMG_OK;
+  });
+}
+
+int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols, int64_t* nnz,
+                         int64_t* rowptr, int32_t* col, double* val) {
+  return guarded([&]() -> int {
+    if (!h || level < 0 || level >= (int)h->host.size() || which < 0 || which > 5)
+      api_fail(CAMG_ERR_INVALID_ARG, "level/which");
+    const HostLevel& L = h->host[level];
+    const HostCSR* M[6] = {&L.K, &L.G, &L.B, &L.C, &L.P_u, &L.P_l};
+    if (which >= 4 && level + 1 >= (int)h->host.size()) api_fail(CAMG_ERR_INVALID_ARG, "no transfer on coarsest");
+    const HostCSR& A = *M[which];
+    if (nrows) *nrows = A.nrows;
+    if (ncols) *ncols = A.ncols;
+    if (nnz) *nnz = A.nnz();
+    if (rowptr) std::copy(A.rp.begin(), A.rp.end(), rowptr);
+    if (col) std::copy(A.ci.begin(), A.ci.end(), col);
+    if (val) std::copy(A.v.begin(), A.v.end(), val);
+    return CAMG_OK;
+  });
+}
+
+int amg_update_fine_values(amg_handle* h, const double* K_val, const double* G_val, const double* B_val,
+                           const double* C_val, void* stream) {
+  return guarded([&]() -> int {
+    if (!h) api_fail(CAMG_ERR_INVALID_ARG, "NULL handle");
+    need_device(h);
+    CAMG_HIP(hipSetDevice(h->device));
+    hipStream_t s = as_stream(stream);
+    DevLevel& D = h->lev[0];
+    struct Item {
+      const double* src;
+      DevMat* M;
+      DevMat* MT;
+      DBuf<int32_t>* perm;
+    } items[4] = {{K_val, &D.K, &D.KT, &h->d_perm_K},
+                  {G_val, &D.G, &D.GT, &h->d_perm_G},
+                  {B_val, &D.B, &D.BT, &h->d_perm_B},
+                  {C_val, &D.C, &D.CT, &h->d_perm_C}};
+    for (auto& it : items) {
+      if (!it.src || it.M->nnz == 0) continue;
+      CAMG_HIP(hipMemcpyAsync(it.M->v64.p, it.src, it.M->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+      scatter_perm<double>(it.src, it.perm->p, it.MT->v64.p, it.M->nnz, s);
+    }
+    return CAMG_OK;
+  });
+}
+
+int amg_apply_operator(amg_handle* h, int transpose, const double* x, double* y, void* stream) {
+  return guarded([&]() -> int {
+    if (!h || !x || !y) api_fail(CAMG_ERR_INVALID_ARG, "NULL argument");
+    need_device(h);
+    CAMG_HIP(hipSetDevice(h->device));
+    apply_op(*h, transpose != 0, x, nullptr, y, as_stream(stream));
+    return CAMG_OK;
+  });
+}
+
+int amg_vcycle_apply(amg_handle* h, int transpose, const double* r, double* z, void* stream) {
+  return guarded([&]() -> int {
+    if (!h || !r || !z) api_fail(CAMG_ERR_INVALID_ARG, "NULL argument");
+    if (r == z) api_fail(CAMG_ERR_INVALID_ARG, "r and z must not overlap");
+    need_device(h);
+    CAMG_HIP(hipSetDevice(h->device));
+    precondition(*h, transpose != 0, r, z, as_stream(stream));
+    return CAMG_OK;
+  });
+}
+
+int fgmres_solve(amg_handle* h, int transpose, const double* b, double* x, const amg_gmres_options* gopts,
+                 amg_gmres_result* res, void* stream) {
+  return guarded([&]() -> int {
+    if (!h || !b || !x) api_fail(CAMG_ERR_INVALID_ARG, "NULL argument");
+    amg_gmres_options o;
+    amg_default_gmres_options(&o);
+    if (gopts) o = *gopts;
+    if (o.m < 1 || o.m > 512 || o.max_iters < 0 || o.fixed_iters < 0 || !(o.rtol >= 0.0))
+      api_fail(CAMG_ERR_INVALID_ARG, "invalid FGMRES options");
+    need_device(h);
+    CAMG_HIP(hipSetDevice(h->device));
+    return gmres(*h, transpose != 0, b, x, o, res, as_stream(stream));
+  });
+}
+
+int amg_grad_K(amg_handle* h, const double* lam, const double* x, double* dK, void* stream) {
+  return guarded([&]() -> int {
+    if (!h || !lam || !x || !dK) api_fail(CAMG_ERR_INVALID_ARG, "NULL argument");
+    need_device(h);
+    CAMG_HIP(hipSetDevice(h->device));
+    grad_K(h->lev[0].K.view<double>(), lam, x, dK, as_stream(stream));
+    return CAMG_OK;
+  });
+}
+
+int amg_profile_enable(amg_handle* h, int mask) {
+  if (!h) return CAMG_ERR_INVALID_ARG;
+  h->prof.mask = mask;
+  return CAMG_OK;
+}
+
+int amg_profile_read(amg_handle* h, int kclass, int64_t* launches, double* total_ms) {
+  return guarded([&]() -> int {
+    if (!h) api_fail(CAMG_ERR_INVALID_ARG, "NULL handle");
+    int64_t cnt = 0;
+    double tot = 0.0;
+    for (auto& r : h->prof.recs) {
+      if (r.cls != kclass) continue;
+      CAMG_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      CAMG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      tot += ms;
+      ++cnt;
+    }
+    if (launches) *launches = cnt;
+    if (total_ms) *total_ms = tot;
+    return CAMG_OK;
+  });
+}
+
+void amg_destroy(amg_handle* h) { delete h; }
+
+const char* amg_strerror(int code) {
+  switch (code) {
+    case CAMG_OK: return "ok";
+    case CAMG_NOT_CONVERGED: return "not converged";
+    case CAMG_ERR_INVALID_ARG: return "invalid argument";
+    case CAMG_ERR_SHAPE: return "shape or structure error";
+    case CAMG_ERR_NONFINITE: return "non-finite value";
+    case CAMG_ERR_ZERO_DIAG: return "zero diagonal";
+    case CAMG_ERR_RANK_DEFICIENT_AGG: return "rank-deficient aggregate";
+    case CAMG_ERR_SINGULAR_COARSE: return "singular coarsest matrix";
+    case CAMG_ERR_HIP: return "HIP error";
+    case CAMG_ERR_OOM: return "out of memory";
+    case CAMG_ERR_UNMAPPED_MULTIPLIER: return "multiplier without slave coupling";
+    default: return "unknown status";
+  }
+}
+
+const char* amg_last_error(void) { return camg::g_last_error.c_str(); }
+
+}  // extern "C"

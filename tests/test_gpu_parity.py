@@ -1,0 +1,301 @@
+"""GPU parity of libcamg against the CPU oracle (run on an MI355X).
+
+Every call goes through the C-ABI (ctypes binding); the oracle runs on the
+CPU on the same seeded inputs.  Tolerances:
+  * FP64 operator apply: 1e-14 relative (only summation order differs);
+  * FP64 V-cycle: 1e-12 relative;
+  * FP64 FGMRES at a fixed iteration count: 1e-10 relative;
+  * mixed FP32/FP64: the solve reaches the same 1e-8 relative residual and
+    the solution differs from a 1e-12 FP64 reference by < 1e-7 relative.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+import torch
+
+from contactgen import make_contact_problem, make_workload
+from oracle.adjoint import grad_K_values, solve as oracle_solve
+from oracle.hierarchy import AMGOptions as OracleOptions
+from oracle.hierarchy import build_hierarchy
+from oracle.vcycle import _apply_A, vcycle as oracle_vcycle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1912_09056_amd.camg import load_library
+
+    load_library()  # fails loudly when the HIP library is missing
+
+
+def _solver(prob, precision=0, **kw):
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
+
+    return AMGSolver.from_problem(prob, AMGOptions(precision=precision, **kw))
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+CASES = {
+    "2d": ("contact2d_16", dict(max_levels=2, nu_pre=1, nu_post=1)),
+    "3d6": ("contact3d_6", dict(max_levels=2)),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    name, kw = CASES[request.param]
+    prob = make_workload(name)
+    lv = build_hierarchy(prob, OracleOptions(**kw))
+    print(f"[case] {name} {kw}", flush=True)
+    return prob, lv, OracleOptions(**kw), kw
+
+
+def test_operator_apply(case):
+    prob, lv, oopts, kw = case
+    s = _solver(prob, **kw)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(prob.n)
+    A = prob.full_matrix()
+    for tr, ref in ((False, A @ x), (True, A.T @ x)):
+        y = s.apply_operator(torch.from_numpy(x), transpose=tr).cpu().numpy()
+        assert _rel(y, ref) < 1e-14
+
+
+def test_vcycle_fp64(case):
+    prob, lv, oopts, kw = case
+    s = _solver(prob, **kw)
+    rng = np.random.default_rng(1)
+    for tr in (False, True):
+        r = rng.standard_normal(prob.n)
+        z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+        ref = oracle_vcycle(lv, r, oopts, transpose=tr)
+        assert _rel(z, ref) < 1e-12, tr
+
+
+def test_vcycle_deterministic(case):
+    prob, lv, oopts, kw = case
+    s = _solver(prob, **kw)
+    r = torch.from_numpy(np.random.default_rng(2).standard_normal(prob.n))
+    z1 = s.vcycle(r).cpu().numpy()
+    z2 = s.vcycle(r).cpu().numpy()
+    assert np.array_equal(z1, z2)
+
+
+def test_vcycle_mixed(case):
+    prob, lv, oopts, kw = case
+    s = _solver(prob, precision=1, **kw)
+    rng = np.random.default_rng(3)
+    for tr in (False, True):
+        r = rng.standard_normal(prob.n)
+        z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+        ref = oracle_vcycle(lv, r, oopts, transpose=tr)
+        assert _rel(z, ref) < 2e-5, tr
+
+
+def test_fgmres_fixed_iterations_fp64(case):
+    prob, lv, oopts, kw = case
+    s = _solver(prob, **kw)
+    for tr in (False, True):
+        for k, m in ((7, 50), (23, 10)):
+            ref = oracle_solve(lv, oopts, prob.b, transpose=tr, m=m, fixed_iters=k)
+            x, info = s.solve(torch.from_numpy(prob.b), transpose=tr, m=m, fixed_iters=k)
+            assert info["iters"] == k
+            assert _rel(x.cpu().numpy(), ref.x) < 1e-10, (tr, k, m)
+            assert abs(info["rel_res_true"] - ref.rel_res_true) <= 1e-8 * ref.rel_res_true + 1e-15
+
+
+def test_fgmres_converges_fp64_and_mixed(case):
+    prob, lv, oopts, kw = case
+    A = prob.full_matrix().tocsc()
+    x_exact = spl.spsolve(A, prob.b)
+    ref = oracle_solve(lv, oopts, prob.b, rtol=1e-8)
+    for prec in (0, 1):
+        s = _solver(prob, precision=prec, **kw)
+        x, info = s.solve(torch.from_numpy(prob.b), rtol=1e-8)
+        x = x.cpu().numpy()
+        print(f"[solve] prec={prec} iters={info['iters']} oracle={ref.iters} rel={info['rel_res_true']:.2e}",
+              flush=True)
+        assert info["converged"] and info["rel_res_true"] <= 1e-8
+        assert np.linalg.norm(prob.b - A @ x) <= 1.0001e-8 * np.linalg.norm(prob.b)
+        if prec == 0:
+            assert abs(info["iters"] - ref.iters) <= 1
+        x12, info12 = s.solve(torch.from_numpy(prob.b), rtol=1e-12)
+        assert info12["converged"]
+        assert _rel(x12.cpu().numpy(), x_exact) < 1e-9
+
+
+def test_mixed_solution_error(case):
+    prob, lv, oopts, kw = case
+    x_ref = oracle_solve(lv, oopts, prob.b, rtol=1e-12).x
+    s = _solver(prob, precision=1, **kw)
+    x, info = s.solve(torch.from_numpy(prob.b), rtol=1e-8)
+    err = _rel(x.cpu().numpy(), x_ref)
+    print(f"[mixed] iters={info['iters']} err_vs_fp64_1e-12={err:.2e}", flush=True)
+    assert info["converged"] and err < 1e-7
+
+
+def test_grad_K_kernel(case):
+    prob, lv, oopts, kw = case
+    s = _solver(prob, **kw)
+    rng = np.random.default_rng(4)
+    lam, x = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    dK = s.grad_K(torch.from_numpy(lam), torch.from_numpy(x)).cpu().numpy()
+    ref = grad_K_values(prob.K, lam[: prob.n_u], x[: prob.n_u])
+    assert np.array_equal(dK, ref)
+
+
+def test_autograd_dense_reference():
+    from paper_1912_09056_amd import contact_solve
+
+    prob = make_workload("contact3d_6")
+    kw = dict(max_levels=2)
+    A = prob.full_matrix().toarray()
+    top = prob.top_dofs
+    x_ref = np.linalg.solve(A, prob.b)
+    g = np.zeros(prob.n)
+    g[top] = x_ref[top]
+    lam_ref = np.linalg.solve(A.T, g)
+    rows = np.repeat(np.arange(prob.n_u), np.diff(prob.K.indptr))
+    gK_ref = -lam_ref[rows] * x_ref[prob.K.indices]
+    for prec in (0, 1):
+        s = _solver(prob, precision=prec, **kw)
+        Kv = torch.tensor(prob.K.data, dtype=torch.float64, device="cuda", requires_grad=True)
+        b = torch.tensor(prob.b, dtype=torch.float64, device="cuda", requires_grad=True)
+        x = contact_solve(s, Kv, b, rtol=1e-12)
+        loss = 0.5 * (x[torch.from_numpy(top).cuda()] ** 2).sum()
+        loss.backward()
+        assert _rel(x.detach().cpu().numpy(), x_ref) < 1e-10
+        assert _rel(b.grad.cpu().numpy(), lam_ref) < 1e-9
+        assert _rel(Kv.grad.cpu().numpy(), gK_ref) < 1e-9
+
+
+def test_finite_differences_gpu():
+    # central differences with step 1e-6 on seeded entries of b and of K's nonzeros;
+    # the bar is 1e-6 of the gradient's largest entry (FD accuracy on stiff entries)
+    from paper_1912_09056_amd import contact_solve
+
+    prob = make_workload("contact3d_6")
+    s = _solver(prob, max_levels=2)
+    top = torch.from_numpy(prob.top_dofs).cuda()
+    Kv0 = torch.tensor(prob.K.data, dtype=torch.float64, device="cuda", requires_grad=True)
+    b0 = torch.tensor(prob.b, dtype=torch.float64, device="cuda", requires_grad=True)
+    x = contact_solve(s, Kv0, b0, rtol=1e-13)
+    (0.5 * (x[top] ** 2).sum()).backward()
+    gb, gK = b0.grad.cpu().numpy(), Kv0.grad.cpu().numpy()
+
+    def loss(Kv, b):
+        with torch.no_grad():
+            xx = contact_solve(s, Kv, b, rtol=1e-13)
+            return 0.5 * float((xx[top] ** 2).sum())
+
+    rng = np.random.default_rng(20)
+    h = 1e-6
+    Kd, bd = Kv0.detach(), b0.detach()
+    for i in rng.choice(np.nonzero(~prob.dirichlet)[0], 5, replace=False):
+        e = torch.zeros_like(bd)
+        e[i] = h
+        fd = (loss(Kd, bd + e) - loss(Kd, bd - e)) / (2 * h)
+        assert abs(fd - gb[i]) <= 1e-6 * np.abs(gb).max()
+    for k in rng.choice(prob.K.nnz, 5, replace=False):
+        e = torch.zeros_like(Kd)
+        e[k] = h
+        fd = (loss(Kd + e, bd) - loss(Kd - e, bd)) / (2 * h)
+        assert abs(fd - gK[k]) <= 1e-6 * np.abs(gK).max()
+    s.update_fine_values(K_val=Kd)
+
+
+def test_edge_cases():
+    from paper_1912_09056_amd.camg import CamgError
+
+    prob = make_workload("contact2d_16")
+    s = _solver(prob, max_levels=2, nu_pre=1, nu_post=1)
+    # zero right-hand side: zero solution, no iteration
+    x, info = s.solve(torch.zeros(prob.n, dtype=torch.float64))
+    assert info["iters"] == 0 and info["converged"] and float(x.abs().max()) == 0.0
+    # iteration limit: status NOT_CONVERGED, last iterate returned
+    x, info = s.solve(torch.from_numpy(prob.b), max_iters=3)
+    assert not info["converged"] and info["iters"] == 3 and info["status"] == 1
+    # non-finite right-hand side
+    bb = prob.b.copy()
+    bb[7] = np.nan
+    with pytest.raises(CamgError) as e:
+        s.solve(torch.from_numpy(bb))
+    assert e.value.code == -3
+    # warm start near the solution: the tolerance is relative to the warm residual
+    xs, _ = s.solve(torch.from_numpy(prob.b), rtol=1e-6)
+    x, info = s.solve(torch.from_numpy(prob.b), x0=xs, rtol=1e-4)
+    assert info["converged"]
+    A = prob.full_matrix()
+    assert np.linalg.norm(prob.b - A @ x.cpu().numpy()) <= 1e-9 * np.linalg.norm(prob.b)
+    # one level: the V-cycle is the direct solve, FGMRES needs one iteration
+    s1 = _solver(prob, max_levels=1)
+    x, info = s1.solve(torch.from_numpy(prob.b))
+    assert info["iters"] == 1 and info["converged"]
+    # singular coarsest matrix is reported at setup
+    pf = make_contact_problem(2, (6, 6), (7, 6), top_bc="free")
+    with pytest.raises(CamgError) as e:
+        _solver(pf, max_levels=1)
+    assert e.value.code == -6
+
+
+def test_three_level_2d_and_restart():
+    prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=5)
+    kw = dict(max_levels=3, max_coarse_rows=50, nu_pre=1, nu_post=1)
+    oopts = OracleOptions(**kw)
+    lv = build_hierarchy(prob, oopts)
+    s = _solver(prob, **kw)
+    r = np.random.default_rng(6).standard_normal(prob.n)
+    assert _rel(s.vcycle(torch.from_numpy(r)).cpu().numpy(), oracle_vcycle(lv, r, oopts)) < 1e-12
+    ref = oracle_solve(lv, oopts, prob.b, m=8, fixed_iters=30)
+    x, info = s.solve(torch.from_numpy(prob.b), m=8, fixed_iters=30)
+    assert info["restarts"] >= 3
+    assert _rel(x.cpu().numpy(), ref.x) < 1e-10
+
+
+def test_jacobi_sweeps_and_diag_options():
+    prob = make_workload("contact2d_16")
+    for kw in (dict(max_levels=2, nu_pre=1, nu_post=2, jacobi_sweeps=2),
+               dict(max_levels=2, nu_pre=2, nu_post=1, jacobi_diag=1, jacobi_omega=0.5, atilde=1)):
+        okw = dict(kw)
+        okw["jacobi_diag"] = "diag" if okw.get("jacobi_diag", 0) == 1 else "atilde"
+        okw["atilde"] = "diag" if okw.get("atilde", 0) == 1 else "rowsum_abs"
+        oopts = OracleOptions(**okw)
+        lv = build_hierarchy(prob, oopts)
+        s = _solver(prob, **kw)
+        r = np.random.default_rng(7).standard_normal(prob.n)
+        for tr in (False, True):
+            z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+            assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < 1e-12, (kw, tr)
+
+
+def test_bench_workload_parity():
+    """The 40^3 / 41x41x40 workload at full size, in the launch configuration the
+    benchmark times: V-cycle (FP64) against the oracle on a seeded vector, and both
+    precisions solving to 1e-8."""
+    prob = make_workload("contact3d_40")
+    kw = dict(max_levels=4)
+    oopts = OracleOptions(**kw)
+    lv = build_hierarchy(prob, oopts)
+    s = _solver(prob, **kw)
+    r = np.random.default_rng(8).standard_normal(prob.n)
+    z = s.vcycle(torch.from_numpy(r)).cpu().numpy()
+    assert _rel(z, oracle_vcycle(lv, r, oopts)) < 1e-12
+    zt = s.vcycle(torch.from_numpy(r), transpose=True).cpu().numpy()
+    assert _rel(zt, oracle_vcycle(lv, r, oopts, transpose=True)) < 1e-12
+    A = prob.full_matrix()
+    for prec in (0, 1):
+        sp_ = _solver(prob, precision=prec, **kw)
+        x, info = sp_.solve(torch.from_numpy(prob.b), rtol=1e-8)
+        print(f"[bench-workload] prec={prec} iters={info['iters']} t={info['seconds']:.4f}s", flush=True)
+        x = x.cpu().numpy()
+        assert info["converged"]
+        assert np.linalg.norm(prob.b - A @ x) <= 1.0001e-8 * np.linalg.norm(prob.b)

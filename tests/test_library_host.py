@@ -1,0 +1,133 @@
+"""CPU tests of libcamg: the library loads and exports every declared
+symbol, and its host-side hierarchy construction (amg_setup_host: no HIP
+call) matches the oracle -- integer outputs bit for bit, Galerkin blocks to
+rounding."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from contactgen import make_contact_problem, make_workload
+from oracle.hierarchy import AMGOptions as OracleOptions
+from oracle.hierarchy import build_hierarchy
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1912_09056_amd", "libcamg.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libcamg.so not built")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "camg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s+(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+
+    from paper_1912_09056_amd import camg
+
+    lib = ctypes.CDLL(LIB)
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(camg.SIGNATURES) == declared
+
+
+def test_strerror_without_gpu():
+    from paper_1912_09056_amd.camg import load_library
+
+    lib = load_library()
+    assert lib.amg_strerror(-6).decode() == "singular coarsest matrix"
+
+
+def _pair(prob, **kw):
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
+
+    lib_opts = AMGOptions(**kw)
+    ora = build_hierarchy(prob, OracleOptions(**kw))
+    lib = AMGSolver.from_problem(prob, lib_opts, host_only=True)
+    return ora, lib
+
+
+CASES = [
+    ("contact2d_16", dict(max_levels=2, nu_pre=1, nu_post=1)),
+    ("contact3d_6", dict(max_levels=2)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES)
+def test_host_hierarchy_matches_oracle(name, kw):
+    prob = make_workload(name)
+    ora, lib = _pair(prob, **kw)
+    assert lib.n_levels == len(ora)
+    for l, L in enumerate(ora):
+        info = lib.level_info(l)
+        assert (info["n_u"], info["n_l"]) == (L.n_u, L.n_l)
+        for blk in ("K", "G", "B", "C"):
+            A = lib.level_matrix(l, blk)
+            R = getattr(L, blk)
+            # identical symbolic pattern, values to rounding
+            assert np.array_equal(A.indptr, R.indptr) and np.array_equal(A.indices, R.indices), (l, blk)
+            scale = max(1.0, np.abs(R.data).max()) if R.nnz else 1.0
+            assert np.abs(A.data - R.data).max(initial=0.0) <= 1e-13 * scale, (l, blk)
+        if l + 1 < len(ora):
+            du, dl = lib.aggregates(l)
+            assert np.array_equal(du, L.agg_u), l
+            assert np.array_equal(dl, L.agg_l), l
+            for blk, R in (("P_u", L.P_u), ("P_l", L.P_l)):
+                A = lib.level_matrix(l, blk)
+                assert np.array_equal(A.indptr, R.indptr) and np.array_equal(A.indices, R.indices)
+                assert np.abs(A.data - R.data).max(initial=0.0) <= 1e-13
+
+
+def test_host_hierarchy_three_levels_2d():
+    prob = make_contact_problem(2, (24, 24), (25, 24))
+    ora, lib = _pair(prob, max_levels=3, max_coarse_rows=50)
+    assert lib.n_levels == len(ora) == 3
+    for l in range(2):
+        du, dl = lib.aggregates(l)
+        assert np.array_equal(du, ora[l].agg_u) and np.array_equal(dl, ora[l].agg_l)
+    Kc = lib.level_matrix(2, "K")
+    assert np.array_equal(Kc.indices, ora[2].K.indices)
+    assert np.abs(Kc.data - ora[2].K.data).max() <= 1e-12 * np.abs(ora[2].K.data).max()
+
+
+@pytest.mark.slow
+def test_host_aggregates_bench_workload():
+    # integer outputs of the 3D 40^3 / 41x41x40 workload, all four levels, bit for bit
+    prob = make_workload("contact3d_40")
+    ora, lib = _pair(prob, max_levels=4)
+    assert lib.n_levels == 4
+    for l in range(3):
+        du, dl = lib.aggregates(l)
+        assert np.array_equal(du, ora[l].agg_u)
+        assert np.array_equal(dl, ora[l].agg_l)
+    sizes = [(lib.level_info(l)["n_u"], lib.level_info(l)["n_l"]) for l in range(4)]
+    assert sizes == [(L.n_u, L.n_l) for L in ora]
+
+
+def test_error_codes_from_host_setup():
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver, CamgError
+
+    p = make_contact_problem(2, (6, 6), (7, 6), top_bc="free")
+    with pytest.raises(CamgError) as e:
+        AMGSolver.from_problem(p, AMGOptions(max_levels=1), host_only=True)
+    assert e.value.code == -6
+    # shape error: multiplier block of the wrong size
+    p = make_workload("contact2d_16")
+    import scipy.sparse as sp
+
+    with pytest.raises(Exception):
+        AMGSolver(2, p.K, p.G, p.B, sp.identity(p.n_lam + 1, format="csr"), p.slave_dofs, p.master_dofs,
+                  host_only=True)
+    # non-finite value
+    K = p.K.copy()
+    K.data[5] = np.nan
+    with pytest.raises(CamgError) as e:
+        AMGSolver(2, K, p.G, p.B, p.C, p.slave_dofs, p.master_dofs, nullspace=p.nullspace, host_only=True)
+    assert e.value.code == -3
