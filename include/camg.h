@@ -92,6 +92,9 @@ typedef struct {
 #define CAMG_JACOBI_DIAG 1       /* Jacobi prediction relaxes with diag(K)  */
 #define CAMG_PREC_FP64 0         /* hierarchy, smoother, transfers in FP64  */
 #define CAMG_PREC_MIXED 1        /* ... in FP32 inside the FP64 FGMRES      */
+#define CAMG_SPMV_AUTO 0         /* K as sliced blocked-ELL on large levels */
+#define CAMG_SPMV_CSR 1          /* K as CSR on every level                 */
+#define CAMG_SPMV_BELL 2         /* K as sliced blocked-ELL on every level  */
 typedef struct {
   int32_t max_levels;      /* >= 1; 1 = direct solve of the whole system  */
   int32_t max_coarse_rows; /* stop coarsening at or below this many rows   */
@@ -100,6 +103,7 @@ typedef struct {
   int32_t atilde;          /* CAMG_ATILDE_*                                */
   int32_t jacobi_diag;     /* CAMG_JACOBI_*                                */
   int32_t precision;       /* CAMG_PREC_*                                  */
+  int32_t spmv_format;     /* CAMG_SPMV_* (storage of K on device)         */
   double jacobi_omega;     /* Jacobi damping                               */
   double simple_alpha;     /* SIMPLE damping (Alg. 3)                      */
 } amg_options;

@@ -67,6 +67,7 @@ class amg_options(Structure):
         ("atilde", c_int32),
         ("jacobi_diag", c_int32),
         ("precision", c_int32),
+        ("spmv_format", c_int32),
         ("jacobi_omega", c_double),
         ("simple_alpha", c_double),
     ]
@@ -185,6 +186,7 @@ class AMGOptions:
     atilde: int = 0
     jacobi_diag: int = 0
     precision: int = PREC_FP64
+    spmv_format: int = 0  # 0 auto, 1 CSR, 2 sliced blocked-ELL
     jacobi_omega: float = 0.8
     simple_alpha: float = 0.8
 

@@ -86,4 +86,18 @@ struct DCSR {
   const T* v = nullptr;
 };
 
+// Device sliced blocked-ELL view of a square node-blocked matrix (bs x bs
+// blocks, node-major dofs).  Slice s holds nodes [64 s, 64 s + 64); its
+// block columns run over positions p in [slice_ptr[s], slice_ptr[s+1]):
+//   bcol[p * 64 + lane]                       block column of node 64 s + lane
+//   val[(p * bs * bs + a * bs + b) * 64 + lane] entry (a, b) of that block
+// Short rows are padded with zero blocks pointing at a valid node.
+template <typename T>
+struct DBELL {
+  int32_t n_nodes = 0, bs = 0, n_slices = 0;
+  const int32_t* slice_ptr = nullptr;
+  const int32_t* bcol = nullptr;
+  const T* val = nullptr;
+};
+
 }  // namespace camg

@@ -258,6 +258,117 @@ __global__ void k_zero(T* __restrict__ y, int64_t n) {
   if (i < n) y[i] = T(0);
 }
 
+
+// ---- sliced blocked-ELL kernels ---------------------------------------------
+
+// Row (node 64*slice + lane, component a) of a BELL matrix times x.  BS > 0
+// is the compile-time block size; BS == 0 reads it at run time.
+template <typename T, int BS>
+__device__ __forceinline__ T bell_row(const DBELL<T>& A, const T* __restrict__ x, int slice, int lane, int a) {
+  const int bs = BS > 0 ? BS : A.bs;
+  const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
+  T acc = T(0);
+#pragma unroll 4
+  for (int p = p0; p < p1; ++p) {
+    const int c = A.bcol[(int64_t)p * 64 + lane];
+    const T* __restrict__ v = A.val + ((int64_t)p * (bs * bs) + a * bs) * 64 + lane;
+    const T* __restrict__ xc = x + (int64_t)c * bs;
+    if (BS > 0) {
+#pragma unroll
+      for (int b = 0; b < BS; ++b) acc += v[b * 64] * xc[b];
+    } else {
+      for (int b = 0; b < bs; ++b) acc += v[b * 64] * xc[b];
+    }
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T csr_row_serial(const DCSR<T>& A, const T* __restrict__ x, int row) {
+  T s = T(0);
+  for (int k = A.rp[row]; k < A.rp[row + 1]; ++k) s += A.v[k] * x[A.ci[k]];
+  return s;
+}
+
+template <typename T, int BS, int MODE>
+__global__ void k_blk_spmv_bell(DBELL<T> K, DCSR<T> A12, DCSR<T> A21, DCSR<T> A22, const T* __restrict__ x1,
+                                const T* __restrict__ x2, const T* __restrict__ b1, const T* __restrict__ b2,
+                                T* __restrict__ y1, T* __restrict__ y2, int n1, int n2) {
+  const int bs = BS > 0 ? BS : K.bs;
+  if ((int)blockIdx.x < K.n_slices) {
+    const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
+    const int slice = blockIdx.x;
+    T s = bell_row<T, BS>(K, x1, slice, lane, a);
+    const int node = slice * 64 + lane;
+    if (node >= K.n_nodes) return;
+    const int row = node * bs + a;
+    if (A12.nnz) s += csr_row_serial<T>(A12, x2, row);
+    if (MODE == 0) y1[row] = s;
+    else if (MODE == 1) y1[row] = b1[row] - s;
+    else y1[row] += s;
+  } else {
+    const int j = ((int)blockIdx.x - K.n_slices) * (int)blockDim.x + threadIdx.x;
+    if (j >= n2) return;
+    T s = T(0);
+    if (A21.nnz) s = csr_row_serial<T>(A21, x1, j);
+    if (A22.nnz) s += csr_row_serial<T>(A22, x2, j);
+    if (MODE == 0) y2[j] = s;
+    else if (MODE == 1) y2[j] = b2[j] - s;
+    else y2[j] += s;
+  }
+}
+
+template <typename T, int BS>
+__global__ void k_smooth_u_bell(DBELL<T> K, DCSR<T> G, const T* __restrict__ zu, const T* __restrict__ zl,
+                                const T* __restrict__ bu, const T* __restrict__ jinv, T omega, T* __restrict__ znu,
+                                T* __restrict__ r_out, T* __restrict__ w_out) {
+  const int bs = BS > 0 ? BS : K.bs;
+  const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
+  const int slice = blockIdx.x;
+  T s = bell_row<T, BS>(K, zu, slice, lane, a);
+  const int node = slice * 64 + lane;
+  if (node >= K.n_nodes) return;
+  const int row = node * bs + a;
+  if (G.nnz) s += csr_row_serial<T>(G, zl, row);
+  const T r = bu[row] - s;
+  const T w = omega * jinv[row] * r;
+  znu[row] = zu[row] + w;
+  if (r_out) {
+    r_out[row] = r;
+    w_out[row] = w;
+  }
+}
+
+template <typename T, int BS>
+__global__ void k_tsmooth_u_bell(DBELL<T> KT, DCSR<T> BT, const T* __restrict__ zu, const T* __restrict__ zl,
+                                 const T* __restrict__ bu, T* __restrict__ su) {
+  const int bs = BS > 0 ? BS : KT.bs;
+  const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
+  const int slice = blockIdx.x;
+  T s = bell_row<T, BS>(KT, zu, slice, lane, a);
+  const int node = slice * 64 + lane;
+  if (node >= KT.n_nodes) return;
+  const int row = node * bs + a;
+  if (BT.nnz) s += csr_row_serial<T>(BT, zl, row);
+  su[row] = bu[row] - s;
+}
+
+template <typename T, int BS>
+__global__ void k_jacobi_extra_bell(DBELL<T> M, const T* __restrict__ w, const T* __restrict__ r,
+                                    const T* __restrict__ jinv, T omega, T* __restrict__ w_out,
+                                    const T* __restrict__ zu, T* __restrict__ znu, int last) {
+  const int bs = BS > 0 ? BS : M.bs;
+  const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
+  const int slice = blockIdx.x;
+  T s = bell_row<T, BS>(M, w, slice, lane, a);
+  const int node = slice * 64 + lane;
+  if (node >= M.n_nodes) return;
+  const int row = node * bs + a;
+  const T wn = w[row] + omega * jinv[row] * (r[row] - s);
+  w_out[row] = wn;
+  if (last) znu[row] = (zu ? zu[row] : T(0)) + wn;
+}
+
 // ---- Krylov -----------------------------------------------------------------
 
 constexpr int kDotGroup = 8;
@@ -396,6 +507,12 @@ __global__ void k_scatter_perm(const double* __restrict__ src, const int32_t* __
                                int64_t nnz) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < nnz) dst[perm[e]] = (T)src[e];
+}
+
+__global__ void k_scatter_pos64(const double* __restrict__ src, const int64_t* __restrict__ pos,
+                                double* __restrict__ dst, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) dst[pos[e]] = src[e];
 }
 
 template <typename T>
@@ -575,6 +692,73 @@ void zero_vec(T* y, int64_t n, hipStream_t s) {
   CAMG_LAUNCHED();
 }
 
+
+#define CAMG_BS_DISPATCH(bs, ...) \
+  switch (bs) {                   \
+    case 2: {                     \
+      constexpr int BS = 2;       \
+      __VA_ARGS__;                \
+    } break;                      \
+    case 3: {                     \
+      constexpr int BS = 3;       \
+      __VA_ARGS__;                \
+    } break;                      \
+    case 6: {                     \
+      constexpr int BS = 6;       \
+      __VA_ARGS__;                \
+    } break;                      \
+    default: {                    \
+      constexpr int BS = 0;       \
+      __VA_ARGS__;                \
+    } break;                      \
+  }
+
+template <typename T>
+void blk_spmv_bell(const DBELL<T>& K, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22, const T* x1,
+                   const T* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2, int mode, hipStream_t s) {
+  const int threads = 64 * K.bs;
+  const int nb_l = (n2 + threads - 1) / threads;
+  dim3 grid(K.n_slices + nb_l);
+  if (grid.x == 0) return;
+  CAMG_BS_DISPATCH(K.bs, {
+    if (mode == 0)
+      k_blk_spmv_bell<T, BS, 0><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2);
+    else if (mode == 1)
+      k_blk_spmv_bell<T, BS, 1><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2);
+    else
+      k_blk_spmv_bell<T, BS, 2><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2);
+  });
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void smooth_u_bell(const DBELL<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* jinv,
+                   T omega, T* znu, T* r_out, T* w_out, int n_u, hipStream_t s) {
+  if (n_u <= 0) return;
+  CAMG_BS_DISPATCH(K.bs, {
+    k_smooth_u_bell<T, BS><<<K.n_slices, 64 * K.bs, 0, s>>>(K, G, zu, zl, bu, jinv, omega, znu, r_out, w_out);
+  });
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void tsmooth_u_bell(const DBELL<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, const T* bu, T* su, int n_u,
+                    hipStream_t s) {
+  if (n_u <= 0) return;
+  CAMG_BS_DISPATCH(KT.bs, { k_tsmooth_u_bell<T, BS><<<KT.n_slices, 64 * KT.bs, 0, s>>>(KT, BT, zu, zl, bu, su); });
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void jacobi_extra_bell(const DBELL<T>& M, const T* w, const T* r, const T* jinv, T omega, T* w_out, const T* zu,
+                       T* znu, bool last, int n_u, hipStream_t s) {
+  if (n_u <= 0) return;
+  CAMG_BS_DISPATCH(M.bs, {
+    k_jacobi_extra_bell<T, BS><<<M.n_slices, 64 * M.bs, 0, s>>>(M, w, r, jinv, omega, w_out, zu, znu, last ? 1 : 0);
+  });
+  CAMG_LAUNCHED();
+}
+
 int mdot_blocks(int64_t n) {
   int64_t nb = (n + 511) / 512;
   return (int)std::max<int64_t>(1, std::min<int64_t>(2048, nb));
@@ -636,6 +820,12 @@ void scatter_perm(const double* src, const int32_t* perm, T* dst, int64_t nnz, h
   CAMG_LAUNCHED();
 }
 
+void scatter_pos64(const double* src, const int64_t* pos, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_scatter_pos64<<<grid_for(n, kBlock), kBlock, 0, s>>>(src, pos, dst, n);
+  CAMG_LAUNCHED();
+}
+
 template <typename T>
 void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
   if (nnz <= 0) return;
@@ -663,6 +853,14 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
   template void copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                                   \
   template void zero_vec<T>(T*, int64_t, hipStream_t);                                                             \
   template void scatter_perm<T>(const double*, const int32_t*, T*, int64_t, hipStream_t);                          \
+  template void blk_spmv_bell<T>(const DBELL<T>&, const DCSR<T>&, const DCSR<T>&, const DCSR<T>&, const T*,        \
+                                 const T*, const T*, const T*, T*, T*, int, int, int, hipStream_t);               \
+  template void smooth_u_bell<T>(const DBELL<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T, T*,   \
+                                 T*, T*, int, hipStream_t);                                                        \
+  template void tsmooth_u_bell<T>(const DBELL<T>&, const DCSR<T>&, const T*, const T*, const T*, T*, int,          \
+                                  hipStream_t);                                                                    \
+  template void jacobi_extra_bell<T>(const DBELL<T>&, const T*, const T*, const T*, T, T*, const T*, T*, bool, int, \
+                                     hipStream_t);                                                                 \
   template void convert_vals<T>(const double*, T*, int64_t, hipStream_t);
 
 CAMG_INSTANTIATE(float)

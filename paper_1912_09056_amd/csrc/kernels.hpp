@@ -62,6 +62,24 @@ template <typename T>
 void tcorrect_u(const DCSR<T>& BT, const T* su, const T* delta, const T* jinv, T omega, T alpha, const T* zu,
                 T* znu, T* t_out, T* w_out, int n_u, bool first, hipStream_t s);
 
+// ---- sliced blocked-ELL (BELL) variants ----------------------------------
+// The displacement rows use K (or K^T) in BELL layout with one thread per
+// (node, component) row: a workgroup of 64*bs threads covers one slice, wave
+// a computes component a of its 64 nodes.  The sparse couplings G, B, C
+// stay CSR (one thread per row; they are short and mostly empty).
+template <typename T>
+void blk_spmv_bell(const DBELL<T>& K, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22, const T* x1,
+                   const T* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2, int mode, hipStream_t s);
+template <typename T>
+void smooth_u_bell(const DBELL<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* jinv,
+                   T omega, T* znu, T* r_out, T* w_out, int n_u, hipStream_t s);
+template <typename T>
+void tsmooth_u_bell(const DBELL<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, const T* bu, T* su, int n_u,
+                    hipStream_t s);
+template <typename T>
+void jacobi_extra_bell(const DBELL<T>& M, const T* w, const T* r, const T* jinv, T omega, T* w_out, const T* zu,
+                       T* znu, bool last, int n_u, hipStream_t s);
+
 // y = M x for a dense row-major n x n matrix (coarsest level).
 template <typename T>
 void dense_gemv(const T* M, const T* x, T* y, int n, hipStream_t s);
@@ -103,6 +121,8 @@ void grad_K(const DCSR<double>& K, const double* lam, const double* x, double* d
 // dst[perm[e]] = src[e] (value refresh of an explicit transpose).
 template <typename T>
 void scatter_perm(const double* src, const int32_t* perm, T* dst, int64_t nnz, hipStream_t s);
+// dst[pos[e]] = src[e] with 64-bit positions (BELL value refresh).
+void scatter_pos64(const double* src, const int64_t* pos, double* dst, int64_t n, hipStream_t s);
 // dst[e] = (T) src[e]
 template <typename T>
 void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s);

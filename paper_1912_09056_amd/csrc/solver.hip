@@ -82,6 +82,101 @@ static void upload_mat(DevMat& D, const HostCSR& H, bool f64, bool f32, hipStrea
   CAMG_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
 }
 
+// Sliced blocked-ELL copy of a square node-blocked CSR matrix.
+struct HostBell {
+  int32_t n_nodes = 0, bs = 0, n_slices = 0;
+  std::vector<int32_t> slice_ptr, bcol;
+  std::vector<double> val;
+  std::vector<int64_t> pos;  // CSR entry -> index into val
+};
+
+static HostBell make_bell(const HostCSR& A, int bs) {
+  HostBell B;
+  B.bs = bs;
+  B.n_nodes = (int32_t)(A.nrows / bs);
+  B.n_slices = (B.n_nodes + 63) / 64;
+  std::vector<int64_t> nptr((size_t)B.n_nodes + 1, 0);
+  std::vector<int32_t> nb;
+  std::vector<int32_t> tmp;
+  for (int32_t i = 0; i < B.n_nodes; ++i) {
+    tmp.clear();
+    for (int a = 0; a < bs; ++a) {
+      const int64_t r = (int64_t)i * bs + a;
+      for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) tmp.push_back(A.ci[k] / bs);
+    }
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    nb.insert(nb.end(), tmp.begin(), tmp.end());
+    nptr[i + 1] = (int64_t)nb.size();
+  }
+  B.slice_ptr.assign((size_t)B.n_slices + 1, 0);
+  for (int32_t sl = 0; sl < B.n_slices; ++sl) {
+    int64_t w = 0;
+    for (int32_t i = sl * 64; i < std::min(B.n_nodes, sl * 64 + 64); ++i) w = std::max(w, nptr[i + 1] - nptr[i]);
+    B.slice_ptr[sl + 1] = B.slice_ptr[sl] + (int32_t)w;
+  }
+  const int64_t npos = B.slice_ptr[B.n_slices];
+  B.bcol.assign((size_t)(npos * 64), 0);
+  B.val.assign((size_t)(npos * 64 * bs * bs), 0.0);
+  for (int32_t i = 0; i < B.n_nodes; ++i) {
+    const int32_t sl = i / 64, lane = i % 64;
+    const int64_t w = B.slice_ptr[sl + 1] - B.slice_ptr[sl];
+    const int64_t cnt = nptr[i + 1] - nptr[i];
+    for (int64_t k = 0; k < w; ++k)
+      B.bcol[(size_t)((B.slice_ptr[sl] + k) * 64 + lane)] = k < cnt ? nb[(size_t)(nptr[i] + k)] : i;
+  }
+  B.pos.resize((size_t)A.nnz());
+  for (int64_t r = 0; r < A.nrows; ++r) {
+    const int32_t i = (int32_t)(r / bs), a = (int32_t)(r % bs);
+    const int32_t sl = i / 64, lane = i % 64;
+    const int32_t* b0 = nb.data() + nptr[i];
+    const int32_t* b1 = nb.data() + nptr[i + 1];
+    for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+      const int32_t bc = A.ci[k] / bs, b = A.ci[k] % bs;
+      const int64_t kk = std::lower_bound(b0, b1, bc) - b0;
+      const int64_t p = B.slice_ptr[sl] + kk;
+      const int64_t idx = (p * bs * bs + a * bs + b) * 64 + lane;
+      B.val[(size_t)idx] = A.v[k];
+      B.pos[(size_t)k] = idx;
+    }
+  }
+  return B;
+}
+
+struct DevBell {
+  int32_t n_nodes = 0, bs = 0, n_slices = 0;
+  DBuf<int32_t> slice_ptr, bcol;
+  DBuf<double> v64;
+  DBuf<float> v32;
+  template <typename T>
+  DBELL<T> view() const {
+    DBELL<T> d;
+    d.n_nodes = n_nodes;
+    d.bs = bs;
+    d.n_slices = n_slices;
+    d.slice_ptr = slice_ptr.p;
+    d.bcol = bcol.p;
+    if constexpr (sizeof(T) == 8) d.val = reinterpret_cast<const T*>(v64.p);
+    else d.val = reinterpret_cast<const T*>(v32.p);
+    return d;
+  }
+};
+
+static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipStream_t s) {
+  D.n_nodes = H.n_nodes;
+  D.bs = H.bs;
+  D.n_slices = H.n_slices;
+  D.slice_ptr.upload(H.slice_ptr, s);
+  D.bcol.upload(H.bcol, s);
+  if (f64) D.v64.upload(H.val, s);
+  if (f32) {
+    std::vector<float> v32(H.val.begin(), H.val.end());
+    D.v32.upload(v32, s);
+    CAMG_HIP(hipStreamSynchronize(s));
+  }
+  CAMG_HIP(hipStreamSynchronize(s));
+}
+
 template <typename T>
 struct LevelVecs {
   DBuf<T> b, z, zn, r, delta, aux1, aux2, su;
@@ -92,6 +187,8 @@ struct LevelVecs {
 struct DevLevel {
   int64_t n_u = 0, n_l = 0;
   DevMat K, G, B, C, KT, GT, BT, CT, Pu, Pl, Ru, Rl;
+  bool bell = false;   // K and K^T in sliced blocked-ELL layout
+  DevBell Kb, KTb;
   DBuf<int32_t> g_rows;
   int32_t n_g_rows = 0;
   int sg_K = 16, sg_R = 16, sg_P = 8;
@@ -157,6 +254,7 @@ struct amg_handle {
   std::vector<DevLevel> lev;
   std::vector<int32_t> perm_K, perm_G, perm_B, perm_C;
   DBuf<int32_t> d_perm_K, d_perm_G, d_perm_B, d_perm_C;
+  DBuf<int64_t> d_bpos_K, d_bpos_KT;  // level-0 K entry -> BELL slot of K / K^T
   int64_t n = 0, n_u = 0, n_l = 0;
   // Krylov workspace
   int m_alloc = 0;
@@ -259,6 +357,27 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
     upload_mat(D.BT, transpose(H.B, perms[2]), f64, f32, s);
     upload_mat(D.CT, transpose(H.C, perms[3]), f64, f32, s);
     D.sg_K = pick_subgroup(H.K.nnz(), H.K.nrows);
+    {
+      const int64_t nodes = H.n_u() / H.bs_u;
+      const int64_t slices = (nodes + 63) / 64;
+      const int fmt = h.opts.spmv_format;
+      D.bell = (fmt == CAMG_SPMV_BELL) || (fmt == CAMG_SPMV_AUTO && slices >= 512);
+      if (D.bell && H.bs_u > 0 && H.n_u() % H.bs_u == 0) {
+        HostBell hb = make_bell(H.K, H.bs_u);
+        HostBell hbt = make_bell(transpose(H.K), H.bs_u);
+        if (l == 0) {
+          std::vector<int64_t> posT((size_t)H.K.nnz());
+          for (int64_t k = 0; k < H.K.nnz(); ++k) posT[(size_t)k] = hbt.pos[(size_t)h.perm_K[(size_t)k]];
+          h.d_bpos_K.upload(hb.pos, s);
+          h.d_bpos_KT.upload(posT, s);
+          CAMG_HIP(hipStreamSynchronize(s));
+        }
+        upload_bell(D.Kb, hb, f64, f32, s);
+        upload_bell(D.KTb, hbt, f64, f32, s);
+      } else {
+        D.bell = false;
+      }
+    }
     if (!coarsest) {
       const bool t64 = !mixed;
       upload_mat(D.Pu, H.P_u, t64, f32, s);
@@ -319,14 +438,22 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   if (!transpose) {
     {
       ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
-      smooth_u<T>(D.K.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, nj > 1 ? V.aux1.p : nullptr,
-                  nj > 1 ? V.aux2.p : nullptr, nu, first, D.sg_K, s);
+      if (D.bell && !first)
+        smooth_u_bell<T>(D.Kb.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, nj > 1 ? V.aux1.p : nullptr,
+                         nj > 1 ? V.aux2.p : nullptr, nu, s);
+      else
+        smooth_u<T>(D.K.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, nj > 1 ? V.aux1.p : nullptr,
+                    nj > 1 ? V.aux2.p : nullptr, nu, first, D.sg_K, s);
     }
     T* wa = V.aux2.p;
     T* wb = V.su.p;
     for (int k = 1; k < nj; ++k) {
-      jacobi_extra<T>(D.K.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
-                      D.sg_K, s);
+      if (D.bell)
+        jacobi_extra_bell<T>(D.Kb.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1,
+                             nu, s);
+      else
+        jacobi_extra<T>(D.K.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
+                        D.sg_K, s);
       std::swap(wa, wb);
     }
     smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, V.sdinv.p, al, znl, V.delta.p, nl, first, s);
@@ -334,7 +461,10 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   } else {
     {
       ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
-      tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, first, D.sg_K, s);
+      if (D.bell && !first)
+        tsmooth_u_bell<T>(D.KTb.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, s);
+      else
+        tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, first, D.sg_K, s);
     }
     tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, V.su.p, V.ainv.p, V.sdinv.p, al, znl, V.delta.p, nl,
                  first, s);
@@ -343,8 +473,12 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
     T* wa = V.aux2.p;
     T* wb = V.r.p;  // r is free during a sweep
     for (int k = 1; k < nj; ++k) {
-      jacobi_extra<T>(D.KT.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
-                      D.sg_K, s);
+      if (D.bell)
+        jacobi_extra_bell<T>(D.KTb.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu,
+                             k == nj - 1, nu, s);
+      else
+        jacobi_extra<T>(D.KT.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
+                        D.sg_K, s);
       std::swap(wa, wb);
     }
   }
@@ -374,7 +508,14 @@ static T* vcycle_level(amg_handle& h, int l, bool transpose, hipStream_t s) {
   if (first) zero_vec<T>(zc, D.n(), s);
   {
     ProfScope ps(l == 0 ? &h.prof : nullptr, CAMG_KCLASS_RESIDUAL, s);
-    if (!transpose)
+    if (D.bell) {
+      if (!transpose)
+        blk_spmv_bell<T>(D.Kb.view<T>(), D.G.view<T>(), D.B.view<T>(), D.C.view<T>(), zc, zc + nu, V.b.p, V.b.p + nu,
+                         V.r.p, V.r.p + nu, nu, nl, 1, s);
+      else
+        blk_spmv_bell<T>(D.KTb.view<T>(), D.BT.view<T>(), D.GT.view<T>(), D.CT.view<T>(), zc, zc + nu, V.b.p,
+                         V.b.p + nu, V.r.p, V.r.p + nu, nu, nl, 1, s);
+    } else if (!transpose)
       blk_spmv<T>(D.K.view<T>(), D.G.view<T>(), D.B.view<T>(), D.C.view<T>(), zc, zc + nu, V.b.p, V.b.p + nu, V.r.p,
                   V.r.p + nu, nu, nl, 1, D.sg_K, s);
     else
@@ -418,7 +559,14 @@ static void apply_op(amg_handle& h, bool transpose, const double* x, const doubl
   const int nu = (int)D.n_u, nl = (int)D.n_l;
   ProfScope ps(&h.prof, CAMG_KCLASS_OPERATOR, s);
   const int mode = b ? 1 : 0;
-  if (!transpose)
+  if (D.bell) {
+    if (!transpose)
+      blk_spmv_bell<double>(D.Kb.view<double>(), D.G.view<double>(), D.B.view<double>(), D.C.view<double>(), x,
+                            x + nu, b, b ? b + nu : nullptr, y, y + nu, nu, nl, mode, s);
+    else
+      blk_spmv_bell<double>(D.KTb.view<double>(), D.BT.view<double>(), D.GT.view<double>(), D.CT.view<double>(), x,
+                            x + nu, b, b ? b + nu : nullptr, y, y + nu, nu, nl, mode, s);
+  } else if (!transpose)
     blk_spmv<double>(D.K.view<double>(), D.G.view<double>(), D.B.view<double>(), D.C.view<double>(), x, x + nu, b,
                      b ? b + nu : nullptr, y, y + nu, nu, nl, mode, D.sg_K, s);
   else
@@ -588,6 +736,7 @@ void amg_default_options(amg_options* o) {
   o->atilde = CAMG_ATILDE_ROWSUM_ABS;
   o->jacobi_diag = CAMG_JACOBI_ATILDE;
   o->precision = CAMG_PREC_FP64;
+  o->spmv_format = CAMG_SPMV_AUTO;
   o->jacobi_omega = 0.8;
   o->simple_alpha = 0.8;
 }
@@ -613,7 +762,7 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   if (p->dim < 1 || p->dim > 3) api_fail(CAMG_ERR_INVALID_ARG, "dim must be 1..3");
   if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
       (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 1 ||
-      o.jacobi_diag < 0 || o.jacobi_diag > 1)
+      o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2)
     api_fail(CAMG_ERR_INVALID_ARG, "invalid options");
   const int64_t nu = p->K.nrows, nl = p->C.nrows;
   if (nu <= 0 || nu % p->dim) api_fail(CAMG_ERR_SHAPE, "n_u must be a positive multiple of dim");
@@ -791,6 +940,10 @@ int amg_update_fine_values(amg_handle* h, const double* K_val, const double* G_v
       if (!it.src || it.M->nnz == 0) continue;
       CAMG_HIP(hipMemcpyAsync(it.M->v64.p, it.src, it.M->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
       scatter_perm<double>(it.src, it.perm->p, it.MT->v64.p, it.M->nnz, s);
+    }
+    if (K_val && D.bell && D.K.nnz) {
+      scatter_pos64(K_val, h->d_bpos_K.p, D.Kb.v64.p, D.K.nnz, s);
+      scatter_pos64(K_val, h->d_bpos_KT.p, D.KTb.v64.p, D.K.nnz, s);
     }
     return CAMG_OK;
   });

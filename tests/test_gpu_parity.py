@@ -32,10 +32,10 @@ def _need_gpu():
     load_library()  # fails loudly when the HIP library is missing
 
 
-def _solver(prob, precision=0, **kw):
+def _solver(prob, precision=0, fmt=0, **kw):
     from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
 
-    return AMGSolver.from_problem(prob, AMGOptions(precision=precision, **kw))
+    return AMGSolver.from_problem(prob, AMGOptions(precision=precision, spmv_format=fmt, **kw))
 
 
 def _rel(a, b):
@@ -44,19 +44,22 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+# (workload, options, K storage on the device: 1 CSR, 2 sliced blocked-ELL)
 CASES = {
-    "2d": ("contact2d_16", dict(max_levels=2, nu_pre=1, nu_post=1)),
-    "3d6": ("contact3d_6", dict(max_levels=2)),
+    "2d-csr": ("contact2d_16", dict(max_levels=2, nu_pre=1, nu_post=1), 1),
+    "2d-bell": ("contact2d_16", dict(max_levels=2, nu_pre=1, nu_post=1), 2),
+    "3d6-csr": ("contact3d_6", dict(max_levels=2), 1),
+    "3d6-bell": ("contact3d_6", dict(max_levels=2), 2),
 }
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
-    name, kw = CASES[request.param]
+    name, kw, fmt = CASES[request.param]
     prob = make_workload(name)
     lv = build_hierarchy(prob, OracleOptions(**kw))
-    print(f"[case] {name} {kw}", flush=True)
-    return prob, lv, OracleOptions(**kw), kw
+    print(f"[case] {name} {kw} fmt={fmt}", flush=True)
+    return prob, lv, OracleOptions(**kw), dict(kw, fmt=fmt)
 
 
 def test_operator_apply(case):
@@ -153,7 +156,8 @@ def test_grad_K_kernel(case):
     assert np.array_equal(dK, ref)
 
 
-def test_autograd_dense_reference():
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_autograd_dense_reference(fmt):
     from paper_1912_09056_amd import contact_solve
 
     prob = make_workload("contact3d_6")
@@ -167,7 +171,7 @@ def test_autograd_dense_reference():
     rows = np.repeat(np.arange(prob.n_u), np.diff(prob.K.indptr))
     gK_ref = -lam_ref[rows] * x_ref[prob.K.indices]
     for prec in (0, 1):
-        s = _solver(prob, precision=prec, **kw)
+        s = _solver(prob, precision=prec, fmt=fmt, **kw)
         Kv = torch.tensor(prob.K.data, dtype=torch.float64, device="cuda", requires_grad=True)
         b = torch.tensor(prob.b, dtype=torch.float64, device="cuda", requires_grad=True)
         x = contact_solve(s, Kv, b, rtol=1e-12)
@@ -178,13 +182,14 @@ def test_autograd_dense_reference():
         assert _rel(Kv.grad.cpu().numpy(), gK_ref) < 1e-9
 
 
-def test_finite_differences_gpu():
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_finite_differences_gpu(fmt):
     # central differences with step 1e-6 on seeded entries of b and of K's nonzeros;
     # the bar is 1e-6 of the gradient's largest entry (FD accuracy on stiff entries)
     from paper_1912_09056_amd import contact_solve
 
     prob = make_workload("contact3d_6")
-    s = _solver(prob, max_levels=2)
+    s = _solver(prob, fmt=fmt, max_levels=2)
     top = torch.from_numpy(prob.top_dofs).cuda()
     Kv0 = torch.tensor(prob.K.data, dtype=torch.float64, device="cuda", requires_grad=True)
     b0 = torch.tensor(prob.b, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -247,12 +252,13 @@ def test_edge_cases():
     assert e.value.code == -6
 
 
-def test_three_level_2d_and_restart():
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_three_level_2d_and_restart(fmt):
     prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=5)
     kw = dict(max_levels=3, max_coarse_rows=50, nu_pre=1, nu_post=1)
     oopts = OracleOptions(**kw)
     lv = build_hierarchy(prob, oopts)
-    s = _solver(prob, **kw)
+    s = _solver(prob, fmt=fmt, **kw)
     r = np.random.default_rng(6).standard_normal(prob.n)
     assert _rel(s.vcycle(torch.from_numpy(r)).cpu().numpy(), oracle_vcycle(lv, r, oopts)) < 1e-12
     ref = oracle_solve(lv, oopts, prob.b, m=8, fixed_iters=30)
@@ -261,7 +267,8 @@ def test_three_level_2d_and_restart():
     assert _rel(x.cpu().numpy(), ref.x) < 1e-10
 
 
-def test_jacobi_sweeps_and_diag_options():
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_jacobi_sweeps_and_diag_options(fmt):
     prob = make_workload("contact2d_16")
     for kw in (dict(max_levels=2, nu_pre=1, nu_post=2, jacobi_sweeps=2),
                dict(max_levels=2, nu_pre=2, nu_post=1, jacobi_diag=1, jacobi_omega=0.5, atilde=1)):
@@ -270,7 +277,7 @@ def test_jacobi_sweeps_and_diag_options():
         okw["atilde"] = "diag" if okw.get("atilde", 0) == 1 else "rowsum_abs"
         oopts = OracleOptions(**okw)
         lv = build_hierarchy(prob, oopts)
-        s = _solver(prob, **kw)
+        s = _solver(prob, fmt=fmt, **kw)
         r = np.random.default_rng(7).standard_normal(prob.n)
         for tr in (False, True):
             z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
@@ -292,10 +299,12 @@ def test_bench_workload_parity():
     zt = s.vcycle(torch.from_numpy(r), transpose=True).cpu().numpy()
     assert _rel(zt, oracle_vcycle(lv, r, oopts, transpose=True)) < 1e-12
     A = prob.full_matrix()
-    for prec in (0, 1):
-        sp_ = _solver(prob, precision=prec, **kw)
+    sc = _solver(prob, fmt=1, **kw)
+    assert _rel(sc.vcycle(torch.from_numpy(r)).cpu().numpy(), z) < 1e-13
+    for prec, fmt in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        sp_ = _solver(prob, precision=prec, fmt=fmt, **kw)
         x, info = sp_.solve(torch.from_numpy(prob.b), rtol=1e-8)
-        print(f"[bench-workload] prec={prec} iters={info['iters']} t={info['seconds']:.4f}s", flush=True)
+        print(f"[bench-workload] prec={prec} fmt={fmt} iters={info['iters']} t={info['seconds']:.4f}s", flush=True)
         x = x.cpu().numpy()
         assert info["converged"]
         assert np.linalg.norm(prob.b - A @ x) <= 1.0001e-8 * np.linalg.norm(prob.b)
