@@ -31,16 +31,59 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times) and exit; used to scale "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
+def copy_probe(mib):
+    import torch
+
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}), flush=True)
+
+
 def smooth_u_bytes(info0, elem):
-    """Algorithmic HBM bytes of one level-0 residual+Jacobi launch (CSR):
-    K and G values and column indices once, row pointers, and the vectors
-    b_u, jinv, z_u (read once), z_l, zn_u (write)."""
+    """Algorithmic HBM bytes of one level-0 residual+Jacobi launch.
+
+    Blocked layout: every nonzero bs x bs block of K once (bs^2 values plus
+    one 4-byte block index; slice padding not counted), G's entries (value +
+    column) and row pointers, and the vectors b_u, jinv, z_u (read once),
+    z_l, zn_u (written).  CSR layout: K's entries (value + column) and row
+    pointers instead of the blocks."""
     n_u, n_l = info0["n_u"], info0["n_l"]
-    nnz = info0["nnz_K"] + info0["nnz_G"]
-    return nnz * (elem + 4) + 2 * (n_u + 1) * 4 + n_u * elem * 4 + n_l * elem
+    vec = n_u * elem * 4 + n_l * elem + info0["nnz_G"] * (elem + 4) + (n_u + 1) * 4
+    if info0["k_layout"] == 1:
+        bs = info0["k_bs"]
+        return info0["k_blocks"] * (bs * bs * elem + 4) + vec
+    return info0["nnz_K"] * (elem + 4) + (n_u + 1) * 4 + vec
+
+
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_smooth_u_bell_contact3d_40.md")
+KERNELS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1912_09056_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 level-0 smoother kernel from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
+    kernel source changed since those counters were taken."""
+    import hashlib
+
+    try:
+        text = open(PROFILE).read()
+        sha = hashlib.sha256(open(KERNELS, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_", "kernel_source")))
+    if vals.get("kernel_source_sha256_16", "").strip() != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch_fp32"])
 
 
 def main():
@@ -48,6 +91,9 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
 
     from contactgen import make_workload
@@ -153,14 +199,19 @@ def main():
         },
         "speedup_mixed_vs_fp64": solve_fp64 / solve_mixed,
         "roofline": {
-            "kernel": "level-0 CheapSIMPLE residual+Jacobi (k_smooth_u, FP32 CSR)",
+            "kernel": "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell: sliced blocked-ELL K)"
+                      if info0["k_layout"] == 1 else "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u: CSR K)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": peak,
             "unit": "GB/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic() if info0["k_layout"] == 1 else None,
             "bytes_per_launch": bytes_per,
+            "bytes_model": "nonzero 3x3 blocks of K (9 FP32 values + 4-byte block index each) + G CSR + "
+                           "5 FP32 vectors of n_u, read or written once",
+            "k_blocks": info0["k_blocks"],
+            "k_slots_with_padding": info0["k_slots"],
             "avg_launch_us": avg_s * 1e6,
             "launches": n_launch,
         },

@@ -131,6 +131,10 @@ typedef struct {
   int64_t n_nodes_u, n_nodes_l;
   int64_t n_agg_u, n_agg_l; /* aggregates built on this level (0 on the coarsest) */
   double op_complexity;   /* sum over levels of nnz / level-0 nnz (all blocks) */
+  int32_t k_layout;       /* device storage of K: 0 CSR, 1 sliced blocked-ELL (-1: host-only handle) */
+  int32_t k_bs;           /* block size of the blocked layout                */
+  int64_t k_blocks;       /* nonzero bs x bs blocks of K (blocked layout)    */
+  int64_t k_slots;        /* stored blocks including slice padding           */
 } amg_level_info;
 
 void amg_default_options(amg_options* opts);

@@ -109,6 +109,10 @@ class amg_level_info(Structure):
         ("n_agg_u", c_int64),
         ("n_agg_l", c_int64),
         ("op_complexity", c_double),
+        ("k_layout", c_int32),
+        ("k_bs", c_int32),
+        ("k_blocks", c_int64),
+        ("k_slots", c_int64),
     ]
 
 

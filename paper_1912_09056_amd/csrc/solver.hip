@@ -85,6 +85,7 @@ static void upload_mat(DevMat& D, const HostCSR& H, bool f64, bool f32, hipStrea
 // Sliced blocked-ELL copy of a square node-blocked CSR matrix.
 struct HostBell {
   int32_t n_nodes = 0, bs = 0, n_slices = 0;
+  int64_t n_blocks = 0;
   std::vector<int32_t> slice_ptr, bcol;
   std::vector<double> val;
   std::vector<int64_t> pos;  // CSR entry -> index into val
@@ -109,6 +110,7 @@ static HostBell make_bell(const HostCSR& A, int bs) {
     nb.insert(nb.end(), tmp.begin(), tmp.end());
     nptr[i + 1] = (int64_t)nb.size();
   }
+  B.n_blocks = (int64_t)nb.size();
   B.slice_ptr.assign((size_t)B.n_slices + 1, 0);
   for (int32_t sl = 0; sl < B.n_slices; ++sl) {
     int64_t w = 0;
@@ -189,6 +191,7 @@ struct DevLevel {
   DevMat K, G, B, C, KT, GT, BT, CT, Pu, Pl, Ru, Rl;
   bool bell = false;   // K and K^T in sliced blocked-ELL layout
   DevBell Kb, KTb;
+  int64_t k_blocks = 0, k_slots = 0;
   DBuf<int32_t> g_rows;
   int32_t n_g_rows = 0;
   int sg_K = 16, sg_R = 16, sg_P = 8;
@@ -374,6 +377,8 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
         }
         upload_bell(D.Kb, hb, f64, f32, s);
         upload_bell(D.KTb, hbt, f64, f32, s);
+        D.k_blocks = hb.n_blocks;
+        D.k_slots = (int64_t)hb.slice_ptr.back() * 64;
       } else {
         D.bell = false;
       }
@@ -886,6 +891,16 @@ int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out) {
     double tot = 0.0;
     for (const auto& X : h->host) tot += (double)X.nnz_all();
     out->op_complexity = tot / (double)h->host[0].nnz_all();
+    out->k_layout = -1;
+    out->k_bs = L.bs_u;
+    out->k_blocks = 0;
+    out->k_slots = 0;
+    if (!h->lev.empty()) {
+      const DevLevel& D = h->lev[level];
+      out->k_layout = D.bell ? 1 : 0;
+      out->k_blocks = D.k_blocks;
+      out->k_slots = D.k_slots;
+    }
     return CAMG_OK;
   });
 }
