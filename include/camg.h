@@ -113,7 +113,7 @@ typedef struct {
   int32_t m;           /* restart length (Krylov vectors per cycle), 1..512 */
   int32_t max_iters;   /* total iteration limit                            */
   int32_t fixed_iters; /* > 0: run exactly this many iterations, ignore rtol */
-  int32_t check_every; /* read the residual estimate every k iterations (>=1) */
+  int32_t check_every; /* reserved (>= 1); the residual estimate of every step is read one step behind */
   double rtol;         /* stop when ||b - A x|| <= rtol ||b - A x0||        */
 } amg_gmres_options;
 

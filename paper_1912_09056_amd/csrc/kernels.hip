@@ -24,6 +24,18 @@ __device__ __forceinline__ T sg_reduce(T v) {
   return v;
 }
 
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = sg_reduce<double, 64>(v);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
+  return t;  // valid in thread 0
+}
+
 template <typename T, int SG>
 __device__ __forceinline__ T row_dot(const DCSR<T>& A, const T* __restrict__ x, int row, int lane) {
   T s = T(0);
@@ -259,6 +271,150 @@ __global__ void k_zero(T* __restrict__ y, int64_t n) {
 }
 
 
+
+// ---- fused CGS2 passes -------------------------------------------------------
+
+constexpr int kCgsBlock = 256;
+
+// Butterfly reduce-scatter across a wave: every lane holds KMAX (a power of
+// two <= 64) values a[0..KMAX); afterwards lane l holds the wave total of
+// coefficient l >> (6 - log2 KMAX).  At the stage with lane offset o each lane
+// keeps one half of its values (the upper half when bit o of its lane id is
+// set), sends the other half to lane l ^ o and adds what it receives: KMAX-1
+// shuffles instead of 6 KMAX for separate trees.  Addition order is fixed.
+// One butterfly stage on the first M entries of a (lane offset O), then the
+// next stage on the half that was kept; unrolled at compile time so the
+// array stays in registers.
+template <int KMAX, int M, int O>
+__device__ __forceinline__ void reduce_scatter_stage(double (&a)[KMAX], int lane) {
+  if constexpr (M > 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < M / 2; ++i) {
+      const double send = up ? a[i] : a[i + M / 2];
+      const double keep = up ? a[i + M / 2] : a[i];
+      a[i] = keep + __shfl_xor(send, O, 64);
+    }
+    reduce_scatter_stage<KMAX, M / 2, O / 2>(a, lane);
+  }
+}
+
+template <int KMAX>
+__device__ __forceinline__ double wave_reduce_scatter(double (&a)[KMAX]) {
+  const int lane = threadIdx.x % 64;
+  reduce_scatter_stage<KMAX, KMAX, 32>(a, lane);
+  double v = a[0];
+  // lanes that share a coefficient (low lane bits) still hold partial sums
+#pragma unroll
+  for (int o = 64 / KMAX / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One Krylov row per thread: the thread keeps its kk basis entries in
+// registers, so pass 2 reads V once for both the update and the new dots.
+// Each workgroup writes partial[k * gridDim.x + blockIdx.x] for its 256 rows
+// (wave shuffle trees, then the four waves in order).
+template <int KMAX, int PASS>
+__global__ void __launch_bounds__(kCgsBlock) k_cgs(const double* __restrict__ V, int64_t ld, int kk,
+                                                   double* __restrict__ w, int64_t n,
+                                                   const double* __restrict__ coef_in, double* __restrict__ partial) {
+  constexpr int NW = kCgsBlock / 64;
+  __shared__ double lds[KMAX * NW];
+  __shared__ double coef[KMAX];
+  if (PASS >= 2) {
+    for (int k = threadIdx.x; k < kk; k += kCgsBlock) coef[k] = coef_in[k];
+    __syncthreads();
+  }
+  const int64_t i = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x;
+  const bool valid = i < n;
+  double v[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) v[k] = (valid && k < kk) ? V[(int64_t)k * ld + i] : 0.0;
+  double wi = valid ? w[i] : 0.0;
+  if (PASS >= 2) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < kk) s += v[k] * coef[k];
+    wi -= s;
+    if (valid) w[i] = wi;
+  }
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (PASS == 3) {
+    const double t = sg_reduce<double, 64>(wi * wi);
+    if (lane == 0) lds[wave] = t;
+  } else {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) v[k] *= wi;
+    const double t = wave_reduce_scatter<KMAX>(v);
+    constexpr int SHIFT = (KMAX == 64) ? 0 : (KMAX == 32) ? 1 : (KMAX == 16) ? 2 : 3;
+    if ((lane & ((1 << SHIFT) - 1)) == 0) lds[(lane >> SHIFT) * NW + wave] = t;
+  }
+  __syncthreads();
+  const int nk = (PASS == 3) ? 1 : kk;
+  for (int k = threadIdx.x; k < nk; k += kCgsBlock) {
+    double t = 0.0;
+    for (int q = 0; q < NW; ++q) t += lds[k * NW + q];
+    partial[(int64_t)k * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Sum of the nb partials of ||w||^2, then Hessenberg column j = kk - 1 from
+// h1 + h2 and ||w||, its Givens rotation and g (one workgroup).
+__global__ void __launch_bounds__(kBlock) k_cgs_finish(const double* __restrict__ partial, int nb, int kk,
+                                                       const double* __restrict__ h1, const double* __restrict__ h2,
+                                                       double* __restrict__ H, int ldh, double* __restrict__ cs,
+                                                       double* __restrict__ sn, double* __restrict__ g,
+                                                       double* __restrict__ res) {
+  __shared__ double lds[kBlock / 64];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc += partial[b];
+  const double hn2 = block_sum(acc, lds);
+  if (threadIdx.x != 0) return;
+  const int j = kk - 1;
+  double* col = H + (int64_t)j * ldh;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double hn = sqrt(hn2);
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double d = hypot(a, b);
+  double c = 1.0, sv = 0.0;
+  if (d != 0.0) {
+    c = a / d;
+    sv = b / d;
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  col[j] = d;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sv * g[j];
+  g[j] = c * g[j];
+  res[0] = fabs(g[j + 1]);
+  res[1] = hn;
+  res[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_arnoldi_prep(const double* __restrict__ w,
+                                                         const double* __restrict__ scale, double* __restrict__ vj,
+                                                         T* __restrict__ b_out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double v;
+  if (scale) {
+    v = w[i] * scale[0];
+    vj[i] = v;
+  } else {
+    v = vj[i];
+  }
+  b_out[i] = (T)v;
+}
+
 // ---- sliced blocked-ELL kernels ---------------------------------------------
 
 // Row (node 64*slice + lane, component a) of a BELL matrix times x.  BS > 0
@@ -373,17 +529,6 @@ __global__ void k_jacobi_extra_bell(DBELL<T> M, const T* __restrict__ w, const T
 
 constexpr int kDotGroup = 8;
 
-__device__ __forceinline__ double block_sum(double v, double* lds) {
-  v = sg_reduce<double, 64>(v);
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  __syncthreads();
-  if (lane == 0) lds[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
-  return t;  // valid in thread 0
-}
 
 __global__ void __launch_bounds__(kBlock) k_mdot_partial(const double* __restrict__ V, int64_t ld, int kk,
                                                          const double* __restrict__ w, int64_t n, int64_t chunk,
@@ -413,6 +558,7 @@ __global__ void __launch_bounds__(kBlock) k_mdot_partial(const double* __restric
 
 __global__ void __launch_bounds__(kBlock) k_mdot_reduce(const double* __restrict__ partial, int nb,
                                                         double* __restrict__ h) {
+  // fixed order: thread t adds entries t, t + 256, ... ; then a fixed tree
   __shared__ double lds[kBlock / 64];
   const int k = blockIdx.x;
   double acc = 0.0;
@@ -759,6 +905,63 @@ void jacobi_extra_bell(const DBELL<T>& M, const T* w, const T* r, const T* jinv,
   CAMG_LAUNCHED();
 }
 
+
+int cgs_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kCgsBlock - 1) / kCgsBlock); }
+
+#define CAMG_KMAX_DISPATCH(kk, ...)  \
+  if (kk <= 8) {                     \
+    constexpr int KMAX = 8;          \
+    __VA_ARGS__;                     \
+  } else if (kk <= 16) {             \
+    constexpr int KMAX = 16;         \
+    __VA_ARGS__;                     \
+  } else if (kk <= 32) {             \
+    constexpr int KMAX = 32;         \
+    __VA_ARGS__;                     \
+  } else {                           \
+    constexpr int KMAX = 64;         \
+    __VA_ARGS__;                     \
+  }
+
+void cgs_pass1(const double* V, int64_t ld, int kk, const double* w, int64_t n, double* partial, double* h1,
+               hipStream_t s) {
+  if (kk < 1 || kk > 64) throw HipError{hipErrorInvalidValue, "cgs_pass1: kk out of range"};
+  const int nb = cgs_blocks(n);
+  CAMG_KMAX_DISPATCH(kk, {
+    k_cgs<KMAX, 1><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, const_cast<double*>(w), n, nullptr, partial);
+  });
+  CAMG_LAUNCHED();
+  k_mdot_reduce<<<kk, kBlock, 0, s>>>(partial, nb, h1);
+  CAMG_LAUNCHED();
+}
+
+void cgs_pass2(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, double* partial,
+               double* h2, hipStream_t s) {
+  if (kk < 1 || kk > 64) throw HipError{hipErrorInvalidValue, "cgs_pass2: kk out of range"};
+  const int nb = cgs_blocks(n);
+  CAMG_KMAX_DISPATCH(kk, { k_cgs<KMAX, 2><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, w, n, h1, partial); });
+  CAMG_LAUNCHED();
+  k_mdot_reduce<<<kk, kBlock, 0, s>>>(partial, nb, h2);
+  CAMG_LAUNCHED();
+}
+
+void cgs_pass3(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, const double* h2,
+               double* partial, double* H, int ldh, double* cs, double* sn, double* g, double* out, hipStream_t s) {
+  if (kk < 1 || kk > 64) throw HipError{hipErrorInvalidValue, "cgs_pass3: kk out of range"};
+  const int nb = cgs_blocks(n);
+  CAMG_KMAX_DISPATCH(kk, { k_cgs<KMAX, 3><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, w, n, h2, partial); });
+  CAMG_LAUNCHED();
+  k_cgs_finish<<<1, kBlock, 0, s>>>(partial, nb, kk, h1, h2, H, ldh, cs, sn, g, out);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void arnoldi_prep(const double* w, const double* scale, double* vj, T* b_out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_arnoldi_prep<T><<<grid_for(n, kBlock), kBlock, 0, s>>>(w, scale, vj, b_out, n);
+  CAMG_LAUNCHED();
+}
+
 int mdot_blocks(int64_t n) {
   int64_t nb = (n + 511) / 512;
   return (int)std::max<int64_t>(1, std::min<int64_t>(2048, nb));
@@ -861,7 +1064,8 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
                                   hipStream_t);                                                                    \
   template void jacobi_extra_bell<T>(const DBELL<T>&, const T*, const T*, const T*, T, T*, const T*, T*, bool, int, \
                                      hipStream_t);                                                                 \
-  template void convert_vals<T>(const double*, T*, int64_t, hipStream_t);
+  template void convert_vals<T>(const double*, T*, int64_t, hipStream_t);                                          \
+  template void arnoldi_prep<T>(const double*, const double*, double*, T*, int64_t, hipStream_t);
 
 CAMG_INSTANTIATE(float)
 CAMG_INSTANTIATE(double)

@@ -116,6 +116,28 @@ void scale_by(const double* x, const double* scale, double* y, int64_t n, hipStr
 // Back substitution H(0:k,0:k) y = g(0:k).
 void hess_solve(const double* H, int ldh, const double* g, double* y, int k, hipStream_t s);
 
+// ---- fused CGS2 passes -------------------------------------------------------
+// Three passes over the Krylov basis V (n x kk, column-major, ld) per
+// Arnoldi step, each followed by a fixed-order reduction of its per-workgroup
+// partial sums:
+//   pass 1: h1 = V^T w
+//   pass 2: w <- w - V h1, h2 = V^T w
+//   pass 3: w <- w - V h2, ||w||, then column j = kk - 1 of the Hessenberg
+//           matrix, its Givens rotation and g (as arnoldi_update; out[0..2]).
+// partial: kk * cgs_blocks(n) doubles.  kk <= 64.
+int cgs_blocks(int64_t n);
+void cgs_pass1(const double* V, int64_t ld, int kk, const double* w, int64_t n, double* partial, double* h1,
+               hipStream_t s);
+void cgs_pass2(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, double* partial,
+               double* h2, hipStream_t s);
+void cgs_pass3(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, const double* h2,
+               double* partial, double* H, int ldh, double* cs, double* sn, double* g, double* out, hipStream_t s);
+// v_j of the Arnoldi basis and the V-cycle input: with scale (device
+// scalar, 1/||w||) given, vj = w * scale is written first; then
+// b_out = (T) vj.  Without scale, vj is only read.
+template <typename T>
+void arnoldi_prep(const double* w, const double* scale, double* vj, T* b_out, int64_t n, hipStream_t s);
+
 // dK[e] = -lam[row(e)] * x[col(e)] over the entries of K.
 void grad_K(const DCSR<double>& K, const double* lam, const double* x, double* dK, hipStream_t s);
 // dst[perm[e]] = src[e] (value refresh of an explicit transpose).

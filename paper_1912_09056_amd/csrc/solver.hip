@@ -2,8 +2,10 @@
 //
 // Host code here only sequences kernels; every vector operation of the
 // solve phase runs on the GPU.  The only per-iteration device-to-host
-// traffic is the Hessenberg residual estimate (and the Arnoldi norm) read
-// every `check_every` iterations.
+// traffic is a 32-byte result block (Hessenberg residual estimate and Arnoldi
+// norm), read one Arnoldi step behind the launches so the device never waits
+// for the host: when step j-1 meets the tolerance, the already launched step
+// j is discarded and never enters the solution.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -262,10 +264,13 @@ struct amg_handle {
   // Krylov workspace
   int m_alloc = 0;
   DBuf<double> V, Z, w, r, H, cs, sn, g, h1, h2, hn2, partial, out, y;
-  double* hbuf = nullptr;  // pinned host mirror of `out`
+  double* hbuf = nullptr;  // pinned host: [0,4) synchronous reads, [4,12) two pipelined slots
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evq[2] = {nullptr, nullptr};
   Prof prof;
   ~amg_handle() {
+    for (auto e : evq)
+      if (e) (void)hipEventDestroy(e);
     if (hbuf) (void)hipHostFree(hbuf);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -558,6 +563,19 @@ static void precondition(amg_handle& h, bool transpose, const double* r, double*
   }
 }
 
+// Runs the V-cycle on the level-0 input already in vecs(0).b and writes the
+// FP64 result to z.
+static void vcycle_to(amg_handle& h, bool transpose, double* z, hipStream_t s) {
+  const int64_t n = h.lev[0].n();
+  if (h.opts.precision == CAMG_PREC_MIXED) {
+    float* out = vcycle_level<float>(h, 0, transpose, s);
+    cast_f2d(out, z, n, s);
+  } else {
+    double* out = vcycle_level<double>(h, 0, transpose, s);
+    copy_vec<double>(out, z, n, s);
+  }
+}
+
 // y = A x, or y = b - A x when b is given (FP64 level-0 operator).
 static void apply_op(amg_handle& h, bool transpose, const double* x, const double* b, double* y, hipStream_t s) {
   DevLevel& D = h.lev[0];
@@ -593,7 +611,7 @@ static void ensure_krylov(amg_handle& h, int m) {
   h.h1.alloc((size_t)(m + 1));
   h.h2.alloc((size_t)(m + 1));
   h.hn2.alloc(1);
-  h.partial.alloc((size_t)((m + 1) * mdot_blocks(n)));
+  h.partial.alloc((size_t)((m + 1) * std::max(mdot_blocks(n), cgs_blocks(n))));
   h.out.alloc(4);
   h.y.alloc((size_t)m);
   h.m_alloc = m;
@@ -611,7 +629,7 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
   ensure_krylov(h, m);
   const bool fixed = o.fixed_iters > 0;
   const int limit = fixed ? o.fixed_iters : o.max_iters;
-  const int check = std::max(1, o.check_every);
+  const double o_rtol = o.rtol;
   CAMG_HIP(hipEventRecord(h.ev0, s));
   // r0 = b - A x0, beta = ||r0||
   apply_op(h, transpose, x, b, h.r.p, s);
@@ -627,35 +645,69 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
     est = true_rel = 0.0;
     status = CAMG_OK;
   } else {
-    for (;;) {
-      int k = 0;
-      bool stop_inner = false;
-      for (int j = 0; j < m && !stop_inner; ++j) {
-        double* vj = h.V.p + (int64_t)j * n;
-        double* zj = h.Z.p + (int64_t)j * n;
-        precondition(h, transpose, vj, zj, s);
-        apply_op(h, transpose, zj, nullptr, h.w.p, s);
-        {
-          ProfScope ps(&h.prof, CAMG_KCLASS_ORTHO, s);
+    const bool fused = (m + 1 <= 64);
+    const bool mixed = h.opts.precision == CAMG_PREC_MIXED;
+    DevLevel& D0 = h.lev[0];
+    // Launches Arnoldi step j: v_j, z_j = M^-1 v_j, w = A z_j, CGS2, Givens;
+    // leaves w / ||w|| scaling for the next step's prep and copies the
+    // 4-double result block to pinned slot j % 2.
+    auto launch_iter = [&](int j) {
+      double* vj = h.V.p + (int64_t)j * n;
+      double* zj = h.Z.p + (int64_t)j * n;
+      const double* scale = j ? h.out.p + 2 : nullptr;
+      if (mixed) arnoldi_prep<float>(h.w.p, scale, vj, D0.v32.b.p, n, s);
+      else arnoldi_prep<double>(h.w.p, scale, vj, D0.v64.b.p, n, s);
+      vcycle_to(h, transpose, zj, s);
+      apply_op(h, transpose, zj, nullptr, h.w.p, s);
+      {
+        ProfScope ps(&h.prof, CAMG_KCLASS_ORTHO, s);
+        if (fused) {
+          cgs_pass1(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h1.p, s);
+          cgs_pass2(h.V.p, n, j + 1, h.w.p, n, h.h1.p, h.partial.p, h.h2.p, s);
+          cgs_pass3(h.V.p, n, j + 1, h.w.p, n, h.h1.p, h.h2.p, h.partial.p, h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p,
+                    h.out.p, s);
+        } else {
           mdot(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h1.p, s);
           gemv_acc(h.V.p, n, j + 1, h.h1.p, -1.0, h.w.p, n, s);
           mdot(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h2.p, s);
           gemv_acc(h.V.p, n, j + 1, h.h2.p, -1.0, h.w.p, n, s);
           mdot(h.w.p, n, 1, h.w.p, n, h.partial.p, h.hn2.p, s);
+          arnoldi_update(h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p, h.h1.p, h.h2.p, h.hn2.p, j, h.out.p, s);
         }
-        arnoldi_update(h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p, h.h1.p, h.h2.p, h.hn2.p, j, h.out.p, s);
-        scale_by(h.w.p, h.out.p + 2, h.V.p + (int64_t)(j + 1) * n, n, s);
+      }
+      double* slot = h.hbuf + 4 + 4 * (j % 2);
+      CAMG_HIP(hipMemcpyAsync(slot, h.out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+      CAMG_HIP(hipEventRecord(h.evq[j % 2], s));
+    };
+    // Reads step j's result (one step behind the launches); true = stop.
+    auto check = [&](int j) -> bool {
+      CAMG_HIP(hipEventSynchronize(h.evq[j % 2]));
+      const double* o = h.hbuf + 4 + 4 * (j % 2);
+      est = o[0] / r0;
+      if (!std::isfinite(est)) api_fail(CAMG_ERR_NONFINITE, "non-finite residual estimate");
+      if (o[1] == 0.0) return true;  // happy breakdown
+      return !fixed && est <= o_rtol;
+    };
+    for (;;) {
+      int k = 0;
+      bool stopped = false;
+      int launched = 0;
+      for (int j = 0; j < m; ++j) {
+        if (total >= limit) break;
+        launch_iter(j);
         ++total;
-        k = j + 1;
-        const bool at_check = (total % check == 0) || (j == m - 1) || (total >= limit);
-        if (at_check) {
-          read_out(h, s);
-          est = h.hbuf[0] / r0;
-          if (!std::isfinite(est)) api_fail(CAMG_ERR_NONFINITE, "non-finite residual estimate");
-          if (h.hbuf[1] == 0.0) stop_inner = true;           // happy breakdown
-          if (!fixed && est <= o.rtol) stop_inner = true;
+        launched = j + 1;
+        if (j >= 1 && check(j - 1)) {
+          // step j was launched speculatively: it never enters the solution
+          --total;
+          k = j;
+          stopped = true;
+          break;
         }
-        if (total >= limit) stop_inner = true;
+      }
+      if (!stopped) {
+        if (launched > 0) (void)check(launched - 1);
+        k = launched;
       }
       hess_solve(h.H.p, m + 1, h.g.p, h.y.p, k, s);
       gemv_acc(h.Z.p, n, k, h.y.p, 1.0, x, n, s);
@@ -854,7 +906,8 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
     CAMG_HIP(hipGetDevice(&h->device));
     CAMG_HIP(hipEventCreate(&h->ev0));
     CAMG_HIP(hipEventCreate(&h->ev1));
-    CAMG_HIP(hipHostMalloc((void**)&h->hbuf, 4 * sizeof(double), hipHostMallocDefault));
+    CAMG_HIP(hipHostMalloc((void**)&h->hbuf, 12 * sizeof(double), hipHostMallocDefault));
+    for (auto& e : h->evq) CAMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     upload_hierarchy(*h, s);
     *out = h.release();
     return CAMG_OK;
