@@ -31,6 +31,7 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--spmv-format", type=int, default=0, help="device storage of K: 0 auto, 1 CSR, 2 blocked-ELL")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times) and exit; used to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -111,7 +112,8 @@ def main():
     solvers = {}
     for name, prec in (("mixed", 1), ("fp64", 0)):
         t1 = time.time()
-        solvers[name] = AMGSolver.from_problem(prob, AMGOptions(max_levels=args.levels, precision=prec))
+        solvers[name] = AMGSolver.from_problem(
+            prob, AMGOptions(max_levels=args.levels, precision=prec, spmv_format=args.spmv_format))
         print(f"[bench] setup {name}: {time.time() - t1:.1f}s levels={solvers[name].n_levels}", file=sys.stderr,
               flush=True)
 

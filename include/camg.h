@@ -104,6 +104,7 @@ typedef struct {
   int32_t jacobi_diag;     /* CAMG_JACOBI_*                                */
   int32_t precision;       /* CAMG_PREC_*                                  */
   int32_t spmv_format;     /* CAMG_SPMV_* (storage of K on device)         */
+  int32_t graphs;          /* 1: capture the V-cycle once into a HIP graph and replay it */
   double jacobi_omega;     /* Jacobi damping                               */
   double simple_alpha;     /* SIMPLE damping (Alg. 3)                      */
 } amg_options;
@@ -113,7 +114,9 @@ typedef struct {
   int32_t m;           /* restart length (Krylov vectors per cycle), 1..512 */
   int32_t max_iters;   /* total iteration limit                            */
   int32_t fixed_iters; /* > 0: run exactly this many iterations, ignore rtol */
-  int32_t check_every; /* reserved (>= 1); the residual estimate of every step is read one step behind */
+  int32_t lookahead;   /* 1..7: the host reads each step's residual estimate this many
+                          steps behind the launches, so the device never waits for the
+                          host; steps launched past convergence are discarded */
   double rtol;         /* stop when ||b - A x|| <= rtol ||b - A x0||        */
 } amg_gmres_options;
 

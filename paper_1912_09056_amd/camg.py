@@ -68,6 +68,7 @@ class amg_options(Structure):
         ("jacobi_diag", c_int32),
         ("precision", c_int32),
         ("spmv_format", c_int32),
+        ("graphs", c_int32),
         ("jacobi_omega", c_double),
         ("simple_alpha", c_double),
     ]
@@ -78,7 +79,7 @@ class amg_gmres_options(Structure):
         ("m", c_int32),
         ("max_iters", c_int32),
         ("fixed_iters", c_int32),
-        ("check_every", c_int32),
+        ("lookahead", c_int32),
         ("rtol", c_double),
     ]
 
@@ -191,6 +192,7 @@ class AMGOptions:
     jacobi_diag: int = 0
     precision: int = PREC_FP64
     spmv_format: int = 0  # 0 auto, 1 CSR, 2 sliced blocked-ELL
+    graphs: int = 1  # replay the V-cycle from a captured HIP graph
     jacobi_omega: float = 0.8
     simple_alpha: float = 0.8
 
@@ -341,12 +343,12 @@ class AMGSolver:
         _check(self.lib.amg_vcycle_apply(self.handle, int(transpose), _dptr(r), _dptr(z), _stream_ptr(stream)))
         return z
 
-    def solve(self, b, x0=None, transpose=False, m=50, rtol=1e-8, max_iters=1000, fixed_iters=0, check_every=1,
+    def solve(self, b, x0=None, transpose=False, m=50, rtol=1e-8, max_iters=1000, fixed_iters=0, lookahead=1,
               stream=None):
         """FGMRES solve; returns (x, result dict)."""
         b = self._vec(b)
         x = self._vec(x0).clone() if x0 is not None else torch.zeros_like(b)
-        go = amg_gmres_options(m, max_iters, fixed_iters, check_every, rtol)
+        go = amg_gmres_options(m, max_iters, fixed_iters, lookahead, rtol)
         res = amg_gmres_result()
         code = _check(self.lib.fgmres_solve(self.handle, int(transpose), _dptr(b), _dptr(x), byref(go), byref(res),
                                             _stream_ptr(stream)))

@@ -272,6 +272,52 @@ __global__ void k_zero(T* __restrict__ y, int64_t n) {
 
 
 
+
+// First forward sweep from z = 0 in two kernels: the multiplier rows form
+// the prediction w = omega * jinv .* b_u on the fly, then the displacement
+// rows apply prediction and correction together.
+template <typename T, int SG>
+__global__ void __launch_bounds__(kBlock) k_smooth_l_first(DCSR<T> B, const T* __restrict__ bu,
+                                                           const T* __restrict__ jinv, T omega,
+                                                           const T* __restrict__ bl, const T* __restrict__ sdinv,
+                                                           T alpha, T* __restrict__ znl, T* __restrict__ delta,
+                                                           int n_l) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n_l) return;
+  T s = T(0);
+  if (B.nnz) {
+    const int e = B.rp[row + 1];
+    for (int k = B.rp[row] + lane; k < e; k += SG) {
+      const int c = B.ci[k];
+      s += B.v[k] * (omega * jinv[c] * bu[c]);
+    }
+  }
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) {
+    const T d = -(bl[row] - s) * sdinv[row];
+    delta[row] = d;
+    znl[row] = alpha * d;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth_u_first_corr(DCSR<T> G, const T* __restrict__ bu,
+                                                                const T* __restrict__ jinv, T omega,
+                                                                const T* __restrict__ delta,
+                                                                const T* __restrict__ ainv, T alpha,
+                                                                T* __restrict__ znu, int n_u) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_u) return;
+  T v = omega * jinv[i] * bu[i];
+  if (G.nnz) {
+    T gd = T(0);
+    for (int k = G.rp[i]; k < G.rp[i + 1]; ++k) gd += G.v[k] * delta[G.ci[k]];
+    v -= alpha * ainv[i] * gd;
+  }
+  znu[i] = v;
+}
+
 // ---- fused CGS2 passes -------------------------------------------------------
 
 constexpr int kCgsBlock = 256;
@@ -446,31 +492,65 @@ __device__ __forceinline__ T csr_row_serial(const DCSR<T>& A, const T* __restric
   return s;
 }
 
-template <typename T, int BS, int MODE>
-__global__ void k_blk_spmv_bell(DBELL<T> K, DCSR<T> A12, DCSR<T> A21, DCSR<T> A22, const T* __restrict__ x1,
-                                const T* __restrict__ x2, const T* __restrict__ b1, const T* __restrict__ b2,
-                                T* __restrict__ y1, T* __restrict__ y2, int n1, int n2) {
+// Row of a BELL matrix times a vector of another precision (converted on
+// load).
+template <typename T, typename XT, int BS>
+__device__ __forceinline__ T bell_row_x(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
+  const int bs = BS > 0 ? BS : A.bs;
+  const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
+  T acc = T(0);
+#pragma unroll 4
+  for (int p = p0; p < p1; ++p) {
+    const int c = A.bcol[(int64_t)p * 64 + lane];
+    const T* __restrict__ v = A.val + ((int64_t)p * (bs * bs) + a * bs) * 64 + lane;
+    const XT* __restrict__ xc = x + (int64_t)c * bs;
+    if (BS > 0) {
+#pragma unroll
+      for (int b = 0; b < BS; ++b) acc += v[b * 64] * (T)xc[b];
+    } else {
+      for (int b = 0; b < bs; ++b) acc += v[b * 64] * (T)xc[b];
+    }
+  }
+  return acc;
+}
+
+template <typename T, typename XT>
+__device__ __forceinline__ T csr_row_serial_x(const DCSR<T>& A, const XT* __restrict__ x, int row) {
+  T s = T(0);
+  for (int k = A.rp[row]; k < A.rp[row + 1]; ++k) s += A.v[k] * (T)x[A.ci[k]];
+  return s;
+}
+
+// Block operator apply with x of type XT (x1 = x, x2 = x + n1).  When xcopy
+// is given, every row also stores its own x entry there in T (a widened
+// copy of x made in the same pass).
+template <typename T, typename XT, int BS, int MODE>
+__global__ void k_blk_spmv_bell(DBELL<T> K, DCSR<T> A12, DCSR<T> A21, DCSR<T> A22, const XT* __restrict__ x1,
+                                const XT* __restrict__ x2, const T* __restrict__ b1, const T* __restrict__ b2,
+                                T* __restrict__ y1, T* __restrict__ y2, int n1, int n2, T* __restrict__ xcopy) {
   const int bs = BS > 0 ? BS : K.bs;
   if ((int)blockIdx.x < K.n_slices) {
     const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
     const int slice = blockIdx.x;
-    T s = bell_row<T, BS>(K, x1, slice, lane, a);
+    T s = bell_row_x<T, XT, BS>(K, x1, slice, lane, a);
     const int node = slice * 64 + lane;
     if (node >= K.n_nodes) return;
     const int row = node * bs + a;
-    if (A12.nnz) s += csr_row_serial<T>(A12, x2, row);
+    if (A12.nnz) s += csr_row_serial_x<T, XT>(A12, x2, row);
     if (MODE == 0) y1[row] = s;
     else if (MODE == 1) y1[row] = b1[row] - s;
     else y1[row] += s;
+    if (xcopy) xcopy[row] = (T)x1[row];
   } else {
     const int j = ((int)blockIdx.x - K.n_slices) * (int)blockDim.x + threadIdx.x;
     if (j >= n2) return;
     T s = T(0);
-    if (A21.nnz) s = csr_row_serial<T>(A21, x1, j);
-    if (A22.nnz) s += csr_row_serial<T>(A22, x2, j);
+    if (A21.nnz) s = csr_row_serial_x<T, XT>(A21, x1, j);
+    if (A22.nnz) s += csr_row_serial_x<T, XT>(A22, x2, j);
     if (MODE == 0) y2[j] = s;
     else if (MODE == 1) y2[j] = b2[j] - s;
     else y2[j] += s;
+    if (xcopy) xcopy[n1 + j] = (T)x2[j];
   }
 }
 
@@ -673,17 +753,28 @@ inline unsigned grid_for(int64_t rows, int rows_per_block) {
 
 }  // namespace
 
+// Lanes per row from the mean row length (measured on the contact
+// hierarchies: long coarse rows prefer many lanes for parallel gathers;
+// rows of at most 8 entries, e.g. tentative prolongators, one thread each).
 int pick_subgroup(int64_t nnz, int64_t nrows) {
   const double avg = nrows ? (double)nnz / (double)nrows : 0.0;
   if (avg > 96.0) return 64;
   if (avg > 40.0) return 32;
   if (avg > 14.0) return 16;
-  if (avg > 5.0) return 8;
-  return 4;
+  if (avg > 8.0) return 8;
+  return 1;
 }
 
 #define CAMG_SG_DISPATCH(sg, ...) \
   switch (sg) {                           \
+    case 1: {                             \
+      constexpr int SG = 1;               \
+      __VA_ARGS__;                        \
+    } break;                              \
+    case 2: {                             \
+      constexpr int SG = 2;               \
+      __VA_ARGS__;                        \
+    } break;                              \
     case 4: {                             \
       constexpr int SG = 4;               \
       __VA_ARGS__;                        \
@@ -859,22 +950,61 @@ void zero_vec(T* y, int64_t n, hipStream_t s) {
     } break;                      \
   }
 
-template <typename T>
-void blk_spmv_bell(const DBELL<T>& K, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22, const T* x1,
-                   const T* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2, int mode, hipStream_t s) {
+template <typename T, typename XT>
+static void blk_spmv_bell_impl(const DBELL<T>& K, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22,
+                               const XT* x1, const XT* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2,
+                               int mode, T* xcopy, hipStream_t s) {
   const int threads = 64 * K.bs;
   const int nb_l = (n2 + threads - 1) / threads;
   dim3 grid(K.n_slices + nb_l);
   if (grid.x == 0) return;
   CAMG_BS_DISPATCH(K.bs, {
     if (mode == 0)
-      k_blk_spmv_bell<T, BS, 0><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2);
+      k_blk_spmv_bell<T, XT, BS, 0><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2,
+                                                              xcopy);
     else if (mode == 1)
-      k_blk_spmv_bell<T, BS, 1><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2);
+      k_blk_spmv_bell<T, XT, BS, 1><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2,
+                                                              xcopy);
     else
-      k_blk_spmv_bell<T, BS, 2><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2);
+      k_blk_spmv_bell<T, XT, BS, 2><<<grid, threads, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2,
+                                                              xcopy);
   });
   CAMG_LAUNCHED();
+}
+
+template <typename T>
+void blk_spmv_bell(const DBELL<T>& K, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22, const T* x1,
+                   const T* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2, int mode, hipStream_t s) {
+  blk_spmv_bell_impl<T, T>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2, mode, nullptr, s);
+}
+
+void op_apply_from_f32(const DBELL<double>& K, const DCSR<double>& A12, const DCSR<double>& A21,
+                       const DCSR<double>& A22, const float* x, double* y, double* xcopy, int n1, int n2,
+                       hipStream_t s) {
+  blk_spmv_bell_impl<double, float>(K, A12, A21, A22, x, x + n1, nullptr, nullptr, y, y + n1, n1, n2, 0, xcopy, s);
+}
+
+void op_apply_copy(const DBELL<double>& K, const DCSR<double>& A12, const DCSR<double>& A21,
+                   const DCSR<double>& A22, const double* x, double* y, double* xcopy, int n1, int n2,
+                   hipStream_t s) {
+  blk_spmv_bell_impl<double, double>(K, A12, A21, A22, x, x + n1, nullptr, nullptr, y, y + n1, n1, n2, 0, xcopy,
+                                     s);
+}
+
+template <typename T>
+void smooth_first(const DCSR<T>& B, const DCSR<T>& G, const T* bu, const T* bl, const T* jinv, const T* ainv,
+                  const T* sdinv, T omega, T alpha, T* znu, T* znl, T* delta, int n_u, int n_l, hipStream_t s) {
+  if (n_l > 0) {
+    constexpr int SG = 8;
+    k_smooth_l_first<T, SG><<<grid_for(n_l, kBlock / SG), kBlock, 0, s>>>(B, bu, jinv, omega, bl, sdinv, alpha,
+                                                                          znl, delta, n_l);
+    CAMG_LAUNCHED();
+  }
+  if (n_u > 0) {
+    k_smooth_u_first_corr<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(G, bu, jinv, omega, delta, ainv, alpha, znu,
+                                                                       n_u);
+    CAMG_LAUNCHED();
+  }
 }
 
 template <typename T>
@@ -1056,6 +1186,8 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
   template void copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                                   \
   template void zero_vec<T>(T*, int64_t, hipStream_t);                                                             \
   template void scatter_perm<T>(const double*, const int32_t*, T*, int64_t, hipStream_t);                          \
+  template void smooth_first<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, const T*,  \
+                                T, T, T*, T*, T*, int, int, hipStream_t);                                          \
   template void blk_spmv_bell<T>(const DBELL<T>&, const DCSR<T>&, const DCSR<T>&, const DCSR<T>&, const T*,        \
                                  const T*, const T*, const T*, T*, T*, int, int, int, hipStream_t);               \
   template void smooth_u_bell<T>(const DBELL<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T, T*,   \

@@ -28,6 +28,13 @@ template <typename T>
 void smooth_u(const DCSR<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* jinv, T omega,
               T* znu, T* r_out, T* w_out, int n_u, bool first, int sg, hipStream_t s);
 
+// First forward sweep from z = 0 (one Jacobi sweep) in two kernels:
+// delta = -(b_l - B (omega*jinv.*b_u)) .* sdinv, zn_l = alpha*delta, then
+// zn_u = omega*jinv.*b_u - alpha*ainv.*(G delta).  delta needs n_l >= 1 entries.
+template <typename T>
+void smooth_first(const DCSR<T>& B, const DCSR<T>& G, const T* bu, const T* bl, const T* jinv, const T* ainv,
+                  const T* sdinv, T omega, T alpha, T* znu, T* znl, T* delta, int n_u, int n_l, hipStream_t s);
+
 // Extra damped-Jacobi sweep on M w = r: w_out = w + omega*jinv*(r - M w);
 // when last, also zn_u = z_u + w_out (z_u null: zn_u = w_out).
 template <typename T>
@@ -79,6 +86,15 @@ void tsmooth_u_bell(const DBELL<T>& KT, const DCSR<T>& BT, const T* zu, const T*
 template <typename T>
 void jacobi_extra_bell(const DBELL<T>& M, const T* w, const T* r, const T* jinv, T omega, T* w_out, const T* zu,
                        T* znu, bool last, int n_u, hipStream_t s);
+
+// FP64 outer operator y = A x (BELL K) reading x in FP32 (the mixed V-cycle
+// output) or FP64, and storing x widened to FP64 in xcopy in the same pass.
+void op_apply_from_f32(const DBELL<double>& K, const DCSR<double>& A12, const DCSR<double>& A21,
+                       const DCSR<double>& A22, const float* x, double* y, double* xcopy, int n1, int n2,
+                       hipStream_t s);
+void op_apply_copy(const DBELL<double>& K, const DCSR<double>& A12, const DCSR<double>& A21,
+                   const DCSR<double>& A22, const double* x, double* y, double* xcopy, int n1, int n2,
+                   hipStream_t s);
 
 // y = M x for a dense row-major n x n matrix (coarsest level).
 template <typename T>

@@ -264,11 +264,22 @@ struct amg_handle {
   // Krylov workspace
   int m_alloc = 0;
   DBuf<double> V, Z, w, r, H, cs, sn, g, h1, h2, hn2, partial, out, y;
-  double* hbuf = nullptr;  // pinned host: [0,4) synchronous reads, [4,12) two pipelined slots
+  double* hbuf = nullptr;  // pinned host: [0,4) synchronous reads, then 4 doubles per pipelined slot
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t evq[2] = {nullptr, nullptr};
+  static constexpr int kSlots = 8;
+  hipEvent_t evq[kSlots] = {};
+  // V-cycle captured once per direction and replayed (graphs option)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t vgraph[2] = {nullptr, nullptr};
+  hipGraphExec_t vexec[2] = {nullptr, nullptr};
+  void* vout[2] = {nullptr, nullptr};
   Prof prof;
   ~amg_handle() {
+    for (int t = 0; t < 2; ++t) {
+      if (vexec[t]) (void)hipGraphExecDestroy(vexec[t]);
+      if (vgraph[t]) (void)hipGraphDestroy(vgraph[t]);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto e : evq)
       if (e) (void)hipEventDestroy(e);
     if (hbuf) (void)hipHostFree(hbuf);
@@ -445,6 +456,11 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   T* znu = zn;
   T* znl = zn + nu;
   Prof* pp = (l == 0) ? &h.prof : nullptr;
+  if (!transpose && first && nj == 1) {
+    smooth_first<T>(D.B.view<T>(), D.G.view<T>(), bu, bl, V.jinv.p, V.ainv.p, V.sdinv.p, om, al, znu, znl,
+                    V.delta.p, nu, nl, s);
+    return;
+  }
   if (!transpose) {
     {
       ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
@@ -469,16 +485,18 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
     smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, V.sdinv.p, al, znl, V.delta.p, nl, first, s);
     correct_u<T>(D.G.view<T>(), D.g_rows.p, D.n_g_rows, V.delta.p, V.ainv.p, al, znu, s);
   } else {
-    {
-      ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
-      if (D.bell && !first)
+    // from z = 0 the adjoint residual is b itself: no first kernel
+    const T* su = first ? bu : V.su.p;
+    if (!first) {
+      ProfScope ps(pp, CAMG_KCLASS_SMOOTH_U, s);
+      if (D.bell)
         tsmooth_u_bell<T>(D.KTb.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, s);
       else
-        tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, first, D.sg_K, s);
+        tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, false, D.sg_K, s);
     }
-    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, V.su.p, V.ainv.p, V.sdinv.p, al, znl, V.delta.p, nl,
-                 first, s);
-    tcorrect_u<T>(D.BT.view<T>(), V.su.p, V.delta.p, V.jinv.p, om, al, zu, znu, nj > 1 ? V.aux1.p : nullptr,
+    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, su, V.ainv.p, V.sdinv.p, al, znl, V.delta.p, nl, first,
+                 s);
+    tcorrect_u<T>(D.BT.view<T>(), su, V.delta.p, V.jinv.p, om, al, zu, znu, nj > 1 ? V.aux1.p : nullptr,
                   nj > 1 ? V.aux2.p : nullptr, nu, first, s);
     T* wa = V.aux2.p;
     T* wb = V.r.p;  // r is free during a sweep
@@ -548,34 +566,56 @@ static T* vcycle_level(amg_handle& h, int l, bool transpose, hipStream_t s) {
   return zc;
 }
 
+// The V-cycle's kernel sequence and buffers are fixed for a handle, so with
+// the graphs option it is captured once per direction (on an internal
+// stream) and replayed on the caller's stream.  Event-based profiling needs
+// the eager path.
+template <typename T>
+static T* vcycle_run(amg_handle& h, bool transpose, hipStream_t s) {
+  if (!h.opts.graphs || h.prof.mask) return vcycle_level<T>(h, 0, transpose, s);
+  const int t = transpose ? 1 : 0;
+  if (!h.vexec[t]) {
+    if (!h.cap_stream) CAMG_HIP(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
+    CAMG_HIP(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal));
+    T* out = nullptr;
+    try {
+      out = vcycle_level<T>(h, 0, transpose, h.cap_stream);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(h.cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    CAMG_HIP(hipStreamEndCapture(h.cap_stream, &h.vgraph[t]));
+    CAMG_HIP(hipGraphInstantiate(&h.vexec[t], h.vgraph[t], nullptr, nullptr, 0));
+    h.vout[t] = out;
+  }
+  CAMG_HIP(hipGraphLaunch(h.vexec[t], s));
+  return reinterpret_cast<T*>(h.vout[t]);
+}
+
+static void vcycle_to(amg_handle& h, bool transpose, double* z, hipStream_t s) {
+  const int64_t n = h.lev[0].n();
+  if (h.opts.precision == CAMG_PREC_MIXED) {
+    float* out = vcycle_run<float>(h, transpose, s);
+    cast_f2d(out, z, n, s);
+  } else {
+    double* out = vcycle_run<double>(h, transpose, s);
+    copy_vec<double>(out, z, n, s);
+  }
+}
+
 // z = M^{-1} r (or M^{-T} r) on FP64 device vectors.
 static void precondition(amg_handle& h, bool transpose, const double* r, double* z, hipStream_t s) {
   DevLevel& D0 = h.lev[0];
   const int64_t n = D0.n();
-  if (h.opts.precision == CAMG_PREC_MIXED) {
-    cast_d2f(r, D0.v32.b.p, n, s);
-    float* out = vcycle_level<float>(h, 0, transpose, s);
-    cast_f2d(out, z, n, s);
-  } else {
-    copy_vec<double>(r, D0.v64.b.p, n, s);
-    double* out = vcycle_level<double>(h, 0, transpose, s);
-    copy_vec<double>(out, z, n, s);
-  }
+  if (h.opts.precision == CAMG_PREC_MIXED) cast_d2f(r, D0.v32.b.p, n, s);
+  else copy_vec<double>(r, D0.v64.b.p, n, s);
+  vcycle_to(h, transpose, z, s);
 }
 
 // Runs the V-cycle on the level-0 input already in vecs(0).b and writes the
 // FP64 result to z.
-static void vcycle_to(amg_handle& h, bool transpose, double* z, hipStream_t s) {
-  const int64_t n = h.lev[0].n();
-  if (h.opts.precision == CAMG_PREC_MIXED) {
-    float* out = vcycle_level<float>(h, 0, transpose, s);
-    cast_f2d(out, z, n, s);
-  } else {
-    double* out = vcycle_level<double>(h, 0, transpose, s);
-    copy_vec<double>(out, z, n, s);
-  }
-}
-
 // y = A x, or y = b - A x when b is given (FP64 level-0 operator).
 static void apply_op(amg_handle& h, bool transpose, const double* x, const double* b, double* y, hipStream_t s) {
   DevLevel& D = h.lev[0];
@@ -630,6 +670,7 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
   const bool fixed = o.fixed_iters > 0;
   const int limit = fixed ? o.fixed_iters : o.max_iters;
   const double o_rtol = o.rtol;
+  const int lag = std::min(std::max(1, o.lookahead), amg_handle::kSlots - 1);
   CAMG_HIP(hipEventRecord(h.ev0, s));
   // r0 = b - A x0, beta = ||r0||
   apply_op(h, transpose, x, b, h.r.p, s);
@@ -657,8 +698,26 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
       const double* scale = j ? h.out.p + 2 : nullptr;
       if (mixed) arnoldi_prep<float>(h.w.p, scale, vj, D0.v32.b.p, n, s);
       else arnoldi_prep<double>(h.w.p, scale, vj, D0.v64.b.p, n, s);
-      vcycle_to(h, transpose, zj, s);
-      apply_op(h, transpose, zj, nullptr, h.w.p, s);
+      if (D0.bell) {
+        // the FP64 operator reads the V-cycle output directly and stores z_j
+        const int nu0 = (int)D0.n_u, nl0 = (int)D0.n_l;
+        const DBELL<double> Kx = transpose ? D0.KTb.view<double>() : D0.Kb.view<double>();
+        const DCSR<double> A12 = transpose ? D0.BT.view<double>() : D0.G.view<double>();
+        const DCSR<double> A21 = transpose ? D0.GT.view<double>() : D0.B.view<double>();
+        const DCSR<double> A22 = transpose ? D0.CT.view<double>() : D0.C.view<double>();
+        if (mixed) {
+          float* out = vcycle_run<float>(h, transpose, s);
+          ProfScope ps(&h.prof, CAMG_KCLASS_OPERATOR, s);
+          op_apply_from_f32(Kx, A12, A21, A22, out, h.w.p, zj, nu0, nl0, s);
+        } else {
+          double* out = vcycle_run<double>(h, transpose, s);
+          ProfScope ps(&h.prof, CAMG_KCLASS_OPERATOR, s);
+          op_apply_copy(Kx, A12, A21, A22, out, h.w.p, zj, nu0, nl0, s);
+        }
+      } else {
+        vcycle_to(h, transpose, zj, s);
+        apply_op(h, transpose, zj, nullptr, h.w.p, s);
+      }
       {
         ProfScope ps(&h.prof, CAMG_KCLASS_ORTHO, s);
         if (fused) {
@@ -675,14 +734,15 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
           arnoldi_update(h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p, h.h1.p, h.h2.p, h.hn2.p, j, h.out.p, s);
         }
       }
-      double* slot = h.hbuf + 4 + 4 * (j % 2);
-      CAMG_HIP(hipMemcpyAsync(slot, h.out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-      CAMG_HIP(hipEventRecord(h.evq[j % 2], s));
+      const int sl = j % amg_handle::kSlots;
+      CAMG_HIP(hipMemcpyAsync(h.hbuf + 4 + 4 * sl, h.out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+      CAMG_HIP(hipEventRecord(h.evq[sl], s));
     };
-    // Reads step j's result (one step behind the launches); true = stop.
+    // Reads step j's result (`lag` steps behind the launches); true = stop.
     auto check = [&](int j) -> bool {
-      CAMG_HIP(hipEventSynchronize(h.evq[j % 2]));
-      const double* o = h.hbuf + 4 + 4 * (j % 2);
+      const int sl = j % amg_handle::kSlots;
+      CAMG_HIP(hipEventSynchronize(h.evq[sl]));
+      const double* o = h.hbuf + 4 + 4 * sl;
       est = o[0] / r0;
       if (!std::isfinite(est)) api_fail(CAMG_ERR_NONFINITE, "non-finite residual estimate");
       if (o[1] == 0.0) return true;  // happy breakdown
@@ -692,22 +752,33 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
       int k = 0;
       bool stopped = false;
       int launched = 0;
+      int checked = 0;  // steps of this cycle whose result has been read
       for (int j = 0; j < m; ++j) {
         if (total >= limit) break;
         launch_iter(j);
         ++total;
         launched = j + 1;
-        if (j >= 1 && check(j - 1)) {
-          // step j was launched speculatively: it never enters the solution
-          --total;
-          k = j;
-          stopped = true;
-          break;
+        if (j - lag >= 0) {
+          ++checked;
+          if (check(j - lag)) {
+            // steps j-lag+1 .. j were launched speculatively: they never
+            // enter the solution
+            total -= lag;
+            k = j - lag + 1;
+            stopped = true;
+            break;
+          }
         }
       }
       if (!stopped) {
-        if (launched > 0) (void)check(launched - 1);
         k = launched;
+        for (int q = checked; q < launched; ++q) {
+          if (check(q)) {
+            total -= launched - (q + 1);
+            k = q + 1;
+            break;
+          }
+        }
       }
       hess_solve(h.H.p, m + 1, h.g.p, h.y.p, k, s);
       gemv_acc(h.Z.p, n, k, h.y.p, 1.0, x, n, s);
@@ -794,6 +865,7 @@ void amg_default_options(amg_options* o) {
   o->jacobi_diag = CAMG_JACOBI_ATILDE;
   o->precision = CAMG_PREC_FP64;
   o->spmv_format = CAMG_SPMV_AUTO;
+  o->graphs = 1;
   o->jacobi_omega = 0.8;
   o->simple_alpha = 0.8;
 }
@@ -803,7 +875,7 @@ void amg_default_gmres_options(amg_gmres_options* o) {
   o->m = 50;
   o->max_iters = 1000;
   o->fixed_iters = 0;
-  o->check_every = 1;
+  o->lookahead = 1;
   o->rtol = 1e-8;
 }
 
@@ -819,7 +891,8 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   if (p->dim < 1 || p->dim > 3) api_fail(CAMG_ERR_INVALID_ARG, "dim must be 1..3");
   if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
       (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 1 ||
-      o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2)
+      o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
+      o.graphs > 1)
     api_fail(CAMG_ERR_INVALID_ARG, "invalid options");
   const int64_t nu = p->K.nrows, nl = p->C.nrows;
   if (nu <= 0 || nu % p->dim) api_fail(CAMG_ERR_SHAPE, "n_u must be a positive multiple of dim");
@@ -906,7 +979,7 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
     CAMG_HIP(hipGetDevice(&h->device));
     CAMG_HIP(hipEventCreate(&h->ev0));
     CAMG_HIP(hipEventCreate(&h->ev1));
-    CAMG_HIP(hipHostMalloc((void**)&h->hbuf, 12 * sizeof(double), hipHostMallocDefault));
+    CAMG_HIP(hipHostMalloc((void**)&h->hbuf, (4 + 4 * amg_handle::kSlots) * sizeof(double), hipHostMallocDefault));
     for (auto& e : h->evq) CAMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     upload_hierarchy(*h, s);
     *out = h.release();

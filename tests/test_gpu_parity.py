@@ -308,3 +308,42 @@ def test_bench_workload_parity():
         x = x.cpu().numpy()
         assert info["converged"]
         assert np.linalg.norm(prob.b - A @ x) <= 1.0001e-8 * np.linalg.norm(prob.b)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replay_matches_eager(prec):
+    """The V-cycle replayed from a captured HIP graph equals the eager launch
+    sequence bit for bit, on every replay, with eager work and
+    synchronisations between replays."""
+    prob = make_workload("contact3d_6")
+    sg = _solver(prob, precision=prec, fmt=2, max_levels=2, graphs=1)
+    se = _solver(prob, precision=prec, fmt=2, max_levels=2, graphs=0)
+    rng = np.random.default_rng(30)
+    for rep in range(5):
+        r = torch.from_numpy(rng.standard_normal(prob.n))
+        for tr in (False, True):
+            zg = sg.vcycle(r, transpose=tr)
+            _ = sg.apply_operator(zg)  # eager work between replays
+            torch.cuda.synchronize()
+            ze = se.vcycle(r, transpose=tr)
+            torch.cuda.synchronize()
+            assert torch.equal(zg.cpu(), ze.cpu()), (rep, tr)
+    xg, ig = sg.solve(torch.from_numpy(prob.b), rtol=1e-10)
+    xe, ie = se.solve(torch.from_numpy(prob.b), rtol=1e-10)
+    assert ig["iters"] == ie["iters"] and torch.equal(xg.cpu(), xe.cpu())
+
+
+def test_lookahead_depth_does_not_change_results():
+    """Reading the residual estimate 1, 2 or 5 steps behind the launches
+    discards the speculative steps: iterates and counts are identical."""
+    prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=9)
+    s = _solver(prob, max_levels=3, max_coarse_rows=50, nu_pre=1, nu_post=1)
+    for m in (8, 50):
+        ref = None
+        for la in (1, 2, 5):
+            x, info = s.solve(torch.from_numpy(prob.b), m=m, rtol=1e-9, lookahead=la)
+            assert info["converged"]
+            if ref is None:
+                ref = (x.cpu(), info["iters"])
+            else:
+                assert info["iters"] == ref[1] and torch.equal(x.cpu(), ref[0]), (la, m)
