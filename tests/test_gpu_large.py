@@ -1,0 +1,136 @@
+"""Full-size checks on the GPU through the C-ABI.
+
+The 40^3 / 41x41x40 gradient check runs with every `-m gpu` invocation.
+The 100^3 and 150^3 workloads take minutes (input generation and host setup
+dominate), so they only run with CAMG_LARGE=1; at those sizes the oracle is
+replaced by properties that hold at any size: the true FP64 residual
+recomputed on the host, agreement of the FP64 and mixed solutions, the
+adjoint identity g.x = lam.b, and the transposed V-cycle's dot-product test.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from contactgen import make_workload
+
+pytestmark = pytest.mark.gpu
+
+LARGE = os.environ.get("CAMG_LARGE") == "1"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1912_09056_amd.camg import load_library
+
+    load_library()
+
+
+def _solver(prob, precision=0, **kw):
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
+
+    return AMGSolver.from_problem(prob, AMGOptions(precision=precision, **kw))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradients_40_central_differences(prec):
+    """40^3 workload: dL/db and dL/dK (L = 0.5 ||u_top||^2) from the adjoint
+    solve against central differences with step 1e-6 on 20 seeded entries of
+    b and 20 of K's nonzeros; bar 1e-6 of the gradient's largest entry."""
+    from paper_1912_09056_amd import contact_solve
+
+    prob = make_workload("contact3d_40")
+    s = _solver(prob, precision=prec, max_levels=4)
+    top = torch.from_numpy(prob.top_dofs).cuda()
+    Kv0 = torch.tensor(prob.K.data, dtype=torch.float64, device="cuda", requires_grad=True)
+    b0 = torch.tensor(prob.b, dtype=torch.float64, device="cuda", requires_grad=True)
+    # 1e-12: the FP64 rounding floor of this operator is about 1e-13
+    x = contact_solve(s, Kv0, b0, rtol=1e-12)
+    (0.5 * (x[top] ** 2).sum()).backward()
+    gb, gK = b0.grad.cpu().numpy(), Kv0.grad.cpu().numpy()
+    Kd, bd = Kv0.detach(), b0.detach()
+    x0 = x.detach()
+
+    def loss(Kv, b):
+        with torch.no_grad():
+            s.update_fine_values(K_val=Kv)
+            # warm start: the initial residual is the O(h) perturbation; reduce it by
+            # 1e-9, but not below the operator's rounding floor (~1e-13 of ||b||)
+            r0 = float((b - s.apply_operator(x0)).norm())
+            rtol = max(1e-9, 2e-13 * float(b.norm()) / r0)
+            xx, info = s.solve(b, x0=x0, rtol=rtol)
+            assert info["converged"], info
+            return 0.5 * float((xx[top] ** 2).sum())
+
+    rng = np.random.default_rng(40)
+    h = 1e-6
+    worst = 0.0
+    for i in rng.choice(np.nonzero(~prob.dirichlet)[0], 20, replace=False):
+        e = torch.zeros_like(bd)
+        e[i] = h
+        fd = (loss(Kd, bd + e) - loss(Kd, bd - e)) / (2 * h)
+        worst = max(worst, abs(fd - gb[i]) / np.abs(gb).max())
+    assert worst <= 1e-6, worst
+    worst = 0.0
+    for k in rng.choice(prob.K.nnz, 20, replace=False):
+        e = torch.zeros_like(Kd)
+        e[k] = h
+        fd = (loss(Kd + e, bd) - loss(Kd - e, bd)) / (2 * h)
+        worst = max(worst, abs(fd - gK[k]) / np.abs(gK).max())
+    s.update_fine_values(K_val=Kd)
+    print(f"[fd40] prec={prec} worst K rel {worst:.2e}", flush=True)
+    assert worst <= 1e-6, worst
+
+
+def _large_case(name, levels):
+    prob = make_workload(name)
+    A = prob.full_matrix()
+    b = torch.from_numpy(prob.b).cuda()
+    top = prob.top_dofs
+    out = {}
+    for prec in (0, 1):
+        s = _solver(prob, precision=prec, max_levels=levels)
+        x, fi = s.solve(b, rtol=1e-8, max_iters=3000)
+        assert fi["converged"], fi
+        xh = x.cpu().numpy()
+        rel = np.linalg.norm(prob.b - A @ xh) / np.linalg.norm(prob.b)
+        assert rel <= 1.0001e-8, rel
+        g = np.zeros(prob.n)
+        g[top] = xh[top]
+        lam, ai = s.solve(torch.from_numpy(g).cuda(), transpose=True, rtol=1e-10, max_iters=3000)
+        assert ai["converged"], ai
+        lamh = lam.cpu().numpy()
+        relT = np.linalg.norm(g - A.T @ lamh) / np.linalg.norm(g)
+        assert relT <= 1.0001e-10, relT
+        # adjoint identity: g.x = lam.b (both sides within the solve tolerances)
+        lhs, rhs = g @ xh, lamh @ prob.b
+        assert abs(lhs - rhs) <= 1e-7 * abs(lhs), (lhs, rhs)
+        # transposed V-cycle is the exact transpose of the forward one
+        rng = np.random.default_rng(3)
+        u = torch.from_numpy(rng.standard_normal(prob.n)).cuda()
+        v = torch.from_numpy(rng.standard_normal(prob.n)).cuda()
+        a1 = float(v @ s.vcycle(u))
+        a2 = float(s.vcycle(v, transpose=True) @ u)
+        tol = 1e-11 if prec == 0 else 1e-4
+        assert abs(a1 - a2) <= tol * abs(a1), (a1, a2)
+        out[prec] = (xh, fi, ai)
+        print(f"[large] {name} prec={prec} fwd iters={fi['iters']} t={fi['seconds']:.3f}s "
+              f"adj iters={ai['iters']} t={ai['seconds']:.3f}s rel={rel:.2e}", flush=True)
+        del s
+        torch.cuda.empty_cache()
+    err = np.linalg.norm(out[1][0] - out[0][0]) / np.linalg.norm(out[0][0])
+    print(f"[large] {name} mixed-vs-fp64 solution difference {err:.2e}", flush=True)
+    assert err < 1e-7
+
+
+@pytest.mark.skipif(not LARGE, reason="set CAMG_LARGE=1 (input generation and setup take minutes)")
+def test_large_100_lognormal():
+    _large_case("contact3d_100_lognormal", 4)
+
+
+@pytest.mark.skipif(not LARGE, reason="set CAMG_LARGE=1 (input generation and setup take minutes)")
+def test_large_150_curved():
+    _large_case("contact3d_150_curved", 5)
