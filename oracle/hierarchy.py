@@ -14,7 +14,11 @@ Paper passages followed:
 * Galerkin coarse blocks and the merged direct solve on the coarsest level
   (weak-scaling study, solver settings);
 * SIMPLEC lumping of |K| and the Schur approximation (Sec. 5.1.3, SIMPLE
-  variants).
+  variants);
+* optionally, smoothed aggregation for the displacement transfers
+  (Sec. 3.1.2, prolongator smoothing equation; the weak-scaling settings
+  smooth the displacement prolongator with omega = 4/3 and keep the
+  multiplier transfers unsmoothed).
 
 Readings where the paper is silent (all listed in the design notes):
 * Dirichlet dof = row of K whose only stored entry is its diagonal and whose
@@ -29,7 +33,15 @@ Readings where the paper is silent (all listed in the design notes):
 * coarse slave / master interface nodes = aggregates containing such nodes;
 * tentative prolongator by per-aggregate modified Gram-Schmidt QR of the
   null-space rows (Dirichlet rows zeroed), columns in order, R_ii > 0;
-* multiplier null space = one constant per Cartesian component.
+* multiplier null space = one constant per Cartesian component;
+* prolongator smoothing divides by the lumped diagonal Atilde = diag(sum_j
+  |K_ij|) instead of diag(K): its spectrum bound lambda(Atilde^-1 K) <= 1
+  lets omega = 4/3 be applied as printed (with diag(K), whose spectrum on
+  hex8 elasticity reaches about 3.15, omega = 4/3 would amplify);
+* the Schur system of the correction step (solved by ILU(0) or KLU in the
+  paper's runs) is either inverted by its diagonal or relaxed by a few
+  undamped Jacobi sweeps with the signed l1 lumping
+  sign(S_jj) sum_k |S_jk|, the Schur analogue of Atilde.
 """
 from __future__ import annotations
 
@@ -50,6 +62,10 @@ class AMGOptions:
     simple_alpha: float = 0.8
     atilde: str = "rowsum_abs"  # or "diag"
     jacobi_diag: str = "atilde"  # relaxation diagonal of the prediction: "atilde" or "diag"
+    prolongator: str = "pa"  # displacement transfers: "pa" tentative, "sa" smoothed
+    sa_omega: float = 4.0 / 3.0  # prolongator smoothing factor (with the lumped diagonal)
+    schur: str = "diag"  # diagonal of the Schur approximation: "diag" or "l1"
+    schur_sweeps: int = 1  # Jacobi sweeps on the Schur system (1 = divide by the diagonal)
 
 
 @dataclass
@@ -74,6 +90,7 @@ class Level:
     dinv: np.ndarray = None
     atilde_inv: np.ndarray = None
     sd_inv: np.ndarray = None
+    S: sp.csr_matrix = None  # Schur approximation B Atilde^-1 G - C (when relaxed by sweeps)
     A_inv: np.ndarray = None  # coarsest level only
     extra: dict = field(default_factory=dict)
 
@@ -255,11 +272,11 @@ def _pattern(M):
     return S
 
 
-def galerkin(R, A, P):
-    """R A P on the symbolic pattern of the product (no numerical dropping)."""
-    S = (_pattern(R) @ _pattern(A) @ _pattern(P)).tocsr()
+def _on_pattern(N, S):
+    """The values of N on the (sorted, wider) pattern S; zeros elsewhere."""
+    S = S.tocsr()
     S.sort_indices()
-    N = (R @ A @ P).tocsr()
+    N = N.tocsr()
     N.sort_indices()
     out = sp.csr_matrix((np.zeros(S.nnz), S.indices.copy(), S.indptr.copy()), shape=S.shape)
     if N.nnz:
@@ -270,6 +287,30 @@ def galerkin(R, A, P):
         assert np.all(key_s[pos] == key_n)
         out.data[pos] = N.data
     return out
+
+
+def galerkin(R, A, P):
+    """R A P on the symbolic pattern of the product (no numerical dropping)."""
+    return _on_pattern(R @ A @ P, _pattern(R) @ _pattern(A) @ _pattern(P))
+
+
+def smoothed_prolongator(K, P_hat, omega):
+    """P = P_hat - omega Atilde^-1 K P_hat (Sec. 3.1.2, prolongator smoothing)
+    with the lumped diagonal Atilde = diag(sum_j |K_ij|), on the symbolic
+    pattern of P_hat plus that of K P_hat."""
+    w = omega / np.asarray(abs(K).sum(axis=1)).ravel()
+    KP = _on_pattern(K @ P_hat, _pattern(K) @ _pattern(P_hat) + _pattern(P_hat))
+    Ph = _on_pattern(P_hat, KP)
+    rows = np.repeat(np.arange(KP.shape[0]), np.diff(KP.indptr))
+    out = KP.copy()
+    out.data = Ph.data - w[rows] * KP.data
+    return out
+
+
+def schur_matrix(L: "Level", At_inv):
+    """B Atilde^-1 G - C on the symbolic pattern of B G plus that of C."""
+    BA = L.B @ sp.diags(At_inv)
+    return _on_pattern(BA @ L.G - L.C, _pattern(L.B) @ _pattern(L.G) + _pattern(L.C))
 
 
 # ----------------------------------------------------------------------------
@@ -288,7 +329,14 @@ def smoother_data(L: Level, opts: AMGOptions):
     diag(K)^-1 K reaches about 3.15), so the default relaxation diagonal is
     the same lumped Atilde, which bounds the spectrum of Atilde^-1 K by one
     for symmetric positive semi-definite K (Gershgorin) and keeps the damped
-    sweep convergent.  "diag" selects plain diag(K)."""
+    sweep convergent.  "diag" selects plain diag(K).
+
+    Schur options: "diag" takes the exact diagonal of the Schur
+    approximation; "l1" the signed absolute row sums sign(S_jj) sum_k |S_jk|,
+    which bound the spectrum of diag^-1 S by one for symmetric positive
+    semi-definite S (as Atilde does for K), so Jacobi sweeps on the Schur
+    system converge even where the mortar coupling M dominates D (a much
+    softer master side).  With schur_sweeps > 1 the matrix itself is kept."""
     dK = L.K.diagonal()
     if np.any(dK == 0.0):
         raise ZeroDivisionError("zero diagonal in K")
@@ -300,8 +348,16 @@ def smoother_data(L: Level, opts: AMGOptions):
         raise ZeroDivisionError("zero Atilde")
     At_inv = 1.0 / At
     # diag(B Atilde^-1 G)_j = sum_i B[j, i] G[i, j] / Atilde_i
-    BG = L.B.multiply(L.G.T.tocsr()).tocsr()
-    Sd = np.asarray(BG @ At_inv).ravel() - L.C.diagonal()
+    if opts.schur == "l1" or opts.schur_sweeps > 1:
+        S = schur_matrix(L, At_inv)
+        if opts.schur == "l1":
+            Sd = np.sign(S.diagonal()) * np.asarray(abs(S).sum(axis=1)).ravel()
+        else:
+            Sd = S.diagonal()
+        L.S = S if opts.schur_sweeps > 1 else None
+    else:
+        BG = L.B.multiply(L.G.T.tocsr()).tocsr()
+        Sd = np.asarray(BG @ At_inv).ravel() - L.C.diagonal()
     if np.any(Sd == 0.0):
         raise ZeroDivisionError("zero Schur diagonal")
     L.dinv = At_inv.copy() if opts.jacobi_diag == "atilde" else 1.0 / dK
@@ -355,8 +411,9 @@ def _level_from_problem(prob) -> Level:
     )
 
 
-def coarsen(L: Level):
+def coarsen(L: Level, opts: AMGOptions = None):
     """Aggregate level L and return the next coarser level."""
+    opts = opts or AMGOptions()
     dirichlet = dirichlet_dofs(L.K, L.G)
     L.dirichlet = dirichlet
     n_nodes = L.n_u // L.bs_u
@@ -374,6 +431,8 @@ def coarsen(L: Level):
     node_of_dof_u = np.arange(L.n_u) // L.bs_u
     P_u, ns_u_c = tentative_prolongator(agg_u, n_agg_u, node_of_dof_u, L.nullspace_u, dirichlet)
     P_l, ns_l_c = tentative_prolongator(agg_l, n_agg_l, L.lm_node, L.nullspace_l, np.zeros(L.n_l, bool))
+    if opts.prolongator == "sa":
+        P_u = smoothed_prolongator(L.K, P_u, opts.sa_omega)
     R_u = P_u.T.tocsr()
     R_l = P_l.T.tocsr()
     L.agg_u, L.agg_l, L.dmap, L.P_u, L.P_l = agg_u, agg_l, dmap, P_u, P_l
@@ -409,7 +468,7 @@ def build_hierarchy(prob, opts: AMGOptions = None, factor_coarsest: bool = True)
     opts = opts or AMGOptions()
     levels = [_level_from_problem(prob)]
     while len(levels) < opts.max_levels and levels[-1].n > opts.max_coarse_rows:
-        nxt = coarsen(levels[-1])
+        nxt = coarsen(levels[-1], opts)
         if nxt.n >= levels[-1].n:
             break
         levels.append(nxt)

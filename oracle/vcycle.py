@@ -37,12 +37,14 @@ def vcycle(levels, b, opts, level=0, transpose=False):
         KT = L.K.T.tocsr()
 
         def sweep(bb, zz):
-            return cheap_simple_sweep_adjoint(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps, KT)
+            return cheap_simple_sweep_adjoint(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps, KT,
+                                              schur_sweeps=opts.schur_sweeps)
     else:
         n_pre, n_post = opts.nu_pre, opts.nu_post
 
         def sweep(bb, zz):
-            return cheap_simple_sweep(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps)
+            return cheap_simple_sweep(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps,
+                                      schur_sweeps=opts.schur_sweeps)
 
     n_u = L.n_u
     z = np.zeros_like(b)

@@ -86,13 +86,20 @@ def test_gradients_40_central_differences(prec):
 
 
 def _large_case(name, levels):
+    import time
+
+    t0 = time.time()
     prob = make_workload(name)
+    print(f"[large] {name}: n={prob.n} nnz(K)={prob.K.nnz} generated in {time.time() - t0:.0f}s", flush=True)
     A = prob.full_matrix()
     b = torch.from_numpy(prob.b).cuda()
     top = prob.top_dofs
     out = {}
     for prec in (0, 1):
+        t0 = time.time()
         s = _solver(prob, precision=prec, max_levels=levels)
+        print(f"[large] {name} prec={prec} setup {time.time() - t0:.0f}s, levels "
+              f"{[s.level_info(l)['n_u'] + s.level_info(l)['n_l'] for l in range(s.n_levels)]}", flush=True)
         x, fi = s.solve(b, rtol=1e-8, max_iters=3000)
         assert fi["converged"], fi
         xh = x.cpu().numpy()

@@ -1,0 +1,148 @@
+"""Pins for the oracle's optional robustness settings (CPU): smoothed
+aggregation for the displacement transfers (Sec. 3.1.2, prolongator
+smoothing; omega = 4/3 as in the weak-scaling settings) and Jacobi sweeps on
+the Schur system with the signed l1-lumped diagonal.  Each pin is a property
+the mathematics fixes independently of the code under test."""
+import numpy as np
+import pytest
+
+from contactgen import make_workload
+from oracle.adjoint import solve
+from oracle.hierarchy import AMGOptions, build_hierarchy, galerkin
+from oracle.smoother import cheap_simple_sweep
+from oracle.vcycle import vcycle
+
+ROBUST = dict(prolongator="sa", schur="l1", schur_sweeps=3, jacobi_sweeps=3)
+
+
+def _cases():
+    return [
+        ("contact2d_16", {}),
+        ("contact3d_6", {}),
+        # the large-contrast workload's material law and curved interface at 6^3
+        ("contact3d_150_curved", dict(slave_elems=(6, 6, 6), master_elems=(7, 7, 6))),
+    ]
+
+
+@pytest.fixture(scope="module", params=_cases(), ids=lambda c: c[0])
+def pair(request):
+    name, kw = request.param
+    p = make_workload(name, **kw)
+    sa = build_hierarchy(p, AMGOptions(max_levels=2, **ROBUST))
+    pa = build_hierarchy(p, AMGOptions(max_levels=2))
+    return p, sa, pa
+
+
+def test_lumped_diagonal_bounds_spectrum(pair):
+    # Gershgorin: every eigenvalue of Atilde^-1 K lies in [-1, 1] for
+    # Atilde = diag(sum_j |K_ij|), so omega = 4/3 never amplifies a mode
+    _, sa, _ = pair
+    K = sa[0].K.toarray()
+    lam = np.linalg.eigvals(K / np.abs(K).sum(axis=1)[:, None]).real
+    assert lam.max() <= 1.0 + 1e-12 and lam.min() >= -1e-12
+
+
+def test_smoothed_prolongator_reproduces_rigid_modes(pair):
+    # wherever K annihilates the rigid body modes (rows away from the
+    # boundary conditions) one damped Jacobi step leaves them unchanged, so
+    # P B_c = B_f there, exactly as for the tentative prolongator
+    _, sa, _ = pair
+    L0, L1 = sa
+    Bf, Bc = L0.nullspace_u, L1.nullspace_u
+    KB = np.abs(L0.K @ Bf).max(axis=1)
+    free = (KB <= 1e-12 * np.abs(L0.K).max() * np.abs(Bf).max()) & ~L0.dirichlet
+    assert free.sum() > L0.n_u // 2
+    err = np.abs((L0.P_u @ Bc - Bf)[free]).max()
+    assert err <= 1e-12 * np.abs(Bf).max()
+    # and the smoothing does change the other rows
+    assert np.abs((L0.P_u @ Bc - Bf)[~free & ~L0.dirichlet]).max() > 1e-6
+
+
+def test_smoothed_prolongator_lowers_column_energy(pair):
+    # ||(I - w Atilde^-1 K) p||_K <= ||p||_K for w = 4/3 because every
+    # eigenvalue mu of Atilde^-1 K is in [0, 1]: |1 - w mu| <= 1
+    _, sa, pa = pair
+    K = sa[0].K
+    Pt, Ps = pa[0].P_u, sa[0].P_u
+    eT = np.einsum("ij,ij->j", Pt.toarray(), (K @ Pt).toarray())
+    eS = np.einsum("ij,ij->j", Ps.toarray(), (K @ Ps).toarray())
+    assert np.all(eS <= eT * (1 + 1e-12))
+    assert np.median(eS / eT) < 0.9
+
+
+def test_smoothed_galerkin_matches_dense_triple_product(pair):
+    _, sa, _ = pair
+    L0, L1 = sa
+    P = L0.P_u.toarray()
+    for blk, Pl, Pr in (("K", P, P), ("G", P, L0.P_l.toarray()), ("B", L0.P_l.toarray(), P)):
+        ref = Pl.T @ getattr(L0, blk).toarray() @ Pr
+        got = getattr(L1, blk).toarray()
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), blk
+    # pattern: symbolic product, so it contains the numerically nonzero entries
+    Kc = galerkin(L0.P_u.T.tocsr(), L0.K, L0.P_u)
+    assert Kc.nnz == L1.K.nnz
+
+
+def test_l1_schur_jacobi_is_convergent(pair):
+    # signed l1 lumping: the Jacobi iteration matrix I - D^-1 S is a
+    # contraction on every case
+    _, sa, _ = pair
+    L = sa[0]
+    S = L.S.toarray()
+    rho = np.abs(np.linalg.eigvals(np.eye(len(S)) - S * L.sd_inv[:, None])).max()
+    assert rho < 0.95
+
+
+def test_diagonal_schur_jacobi_diverges_under_contrast():
+    # the reason for the l1 option: on the lognormal(0, 2) curved case the
+    # exact diagonal of S gives a Jacobi iteration matrix with spectral
+    # radius above one (the mortar M couplings dominate D where the master
+    # side is much softer), while the l1 lumping stays a contraction
+    p = make_workload("contact3d_150_curved", slave_elems=(10, 10, 10), master_elems=(11, 11, 10))
+    L = build_hierarchy(p, AMGOptions(max_levels=2, schur="diag", schur_sweeps=2))[0]
+    S = L.S.toarray()
+    I = np.eye(len(S))
+    rho_diag = np.abs(np.linalg.eigvals(I - S / np.diag(S)[:, None])).max()
+    L1 = build_hierarchy(p, AMGOptions(max_levels=2, schur="l1", schur_sweeps=2))[0]
+    rho_l1 = np.abs(np.linalg.eigvals(I - S * L1.sd_inv[:, None])).max()
+    assert rho_diag > 1.05 and rho_l1 < 0.95
+
+
+def test_many_schur_sweeps_give_exact_simple_constraints():
+    # with alpha = 1 and the exact Schur complement of the lumped system the
+    # constraint rows hold after one sweep whatever the prediction
+    # (Sec. 5.1.3); enough l1 Jacobi sweeps on S reproduce that to rounding
+    p = make_workload("contact3d_6")
+    L = build_hierarchy(p, AMGOptions(max_levels=2, schur="l1", schur_sweeps=80))[0]
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(L.n)
+    z = cheap_simple_sweep(L, b, np.zeros(L.n), 0.8, 1.0, schur_sweeps=80)
+    rl = b[L.n_u:] - (L.B @ z[: L.n_u] + L.C @ z[L.n_u:])
+    assert np.abs(rl).max() <= 1e-12 * np.abs(b).max()
+    # one sweep (plain division) does not
+    z1 = cheap_simple_sweep(L, b, np.zeros(L.n), 0.8, 1.0, schur_sweeps=1)
+    rl1 = b[L.n_u:] - (L.B @ z1[: L.n_u] + L.C @ z1[L.n_u:])
+    assert np.abs(rl1).max() > 1e-4 * np.abs(b).max()
+
+
+def test_robust_vcycle_transpose_dot_product(pair):
+    _, sa, _ = pair
+    o = AMGOptions(max_levels=2, **ROBUST)
+    n = sa[0].n
+    rng = np.random.default_rng(11)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    a1 = y @ vcycle(sa, x, o)
+    a2 = vcycle(sa, y, o, transpose=True) @ x
+    assert abs(a1 - a2) <= 1e-12 * abs(a1)
+
+
+def test_robust_settings_converge_under_contrast():
+    # the lognormal(0, 2) curved case at 10^3: the robust settings converge in
+    # fewer iterations than the plain ones (whose smoother diverges there)
+    p = make_workload("contact3d_150_curved", slave_elems=(10, 10, 10), master_elems=(11, 11, 10))
+    o = AMGOptions(max_levels=2, prolongator="sa", schur="l1", schur_sweeps=2, jacobi_sweeps=3)
+    r = solve(build_hierarchy(p, o), o, p.b, rtol=1e-8, max_iters=400)
+    base = AMGOptions(max_levels=2)
+    r0 = solve(build_hierarchy(p, base), base, p.b, rtol=1e-8, max_iters=400)
+    assert r.converged and r.rel_res_true <= 1e-8
+    assert r.iters < r0.iters
