@@ -95,6 +95,10 @@ typedef struct {
 #define CAMG_SPMV_AUTO 0         /* K as sliced blocked-ELL on large levels */
 #define CAMG_SPMV_CSR 1          /* K as CSR on every level                 */
 #define CAMG_SPMV_BELL 2         /* K as sliced blocked-ELL on every level  */
+#define CAMG_PROLONG_TENTATIVE 0 /* displacement transfers: tentative (PA)  */
+#define CAMG_PROLONG_SMOOTHED 1  /* ... smoothed aggregation (SA)           */
+#define CAMG_SCHUR_DIAG 0        /* Schur diagonal: diag(B Atilde^-1 G - C) */
+#define CAMG_SCHUR_L1 1          /* ... signed l1 row sums of that matrix   */
 typedef struct {
   int32_t max_levels;      /* >= 1; 1 = direct solve of the whole system  */
   int32_t max_coarse_rows; /* stop coarsening at or below this many rows   */
@@ -107,6 +111,20 @@ typedef struct {
   int32_t graphs;          /* 1: capture the V-cycle once into a HIP graph and replay it */
   double jacobi_omega;     /* Jacobi damping                               */
   double simple_alpha;     /* SIMPLE damping (Alg. 3)                      */
+  /* Robustness settings for strong stiffness contrast (defaults keep the
+   * plain method):
+   * prolongator: CAMG_PROLONG_SMOOTHED smooths the displacement transfers,
+   *   P = P_tent - sa_omega Atilde^-1 K P_tent (Sec. 3.1.2, prolongator
+   *   smoothing; the weak-scaling settings use 4/3), with the lumped
+   *   diagonal Atilde = diag(sum_j |K_ij|); multiplier transfers stay
+   *   tentative.
+   * schur / schur_sweeps: the correction step solves S delta = -r with
+   *   S = B Atilde^-1 G - C by schur_sweeps undamped Jacobi sweeps from zero
+   *   (1 = division by the diagonal), the diagonal chosen by CAMG_SCHUR_*. */
+  int32_t prolongator;     /* CAMG_PROLONG_*                               */
+  int32_t schur;           /* CAMG_SCHUR_*                                 */
+  int32_t schur_sweeps;    /* 1..64                                        */
+  double sa_omega;         /* prolongator smoothing factor, > 0            */
 } amg_options;
 
 /* FGMRES options. */
@@ -165,17 +183,19 @@ int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out);
  * Either pointer may be NULL. */
 int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_t* lm_agg);
 
-/* Copies block `which` (0=K, 1=G, 2=B, 3=C, 4=P_u, 5=P_l) of `level` to host
- * arrays in FP64 (rowptr: nrows+1, col/val: nnz).  Call with NULL arrays to
- * query *nrows, *ncols, *nnz first. */
+/* Copies block `which` (0=K, 1=G, 2=B, 3=C, 4=P_u, 5=P_l, 6=S, the Schur
+ * matrix B Atilde^-1 G - C kept when schur_sweeps > 1, else 0 x 0) of
+ * `level` to host arrays in FP64 (rowptr: nrows+1, col/val: nnz).  Call with
+ * NULL arrays to query *nrows, *ncols, *nnz first. */
 int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols,
                          int64_t* nnz, int64_t* rowptr, int32_t* col, double* val);
 
 /* Replaces the values of the level-0 blocks (device pointers, FP64, same
  * patterns and order as at setup; NULL keeps a block).  The outer FGMRES
  * operator and the FP64 level-0 smoother operator use the new values; the
- * coarse levels, the smoother diagonals and an FP32 level-0 copy keep the
- * setup-time values (a fixed preconditioner for the new operator). */
+ * coarse levels, the smoother diagonals, the Schur matrix and an FP32
+ * level-0 copy keep the setup-time values (a fixed preconditioner for the
+ * new operator). */
 int amg_update_fine_values(amg_handle* h, const double* K_val, const double* G_val, const double* B_val,
                            const double* C_val, void* hip_stream);
 

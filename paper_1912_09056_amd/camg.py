@@ -71,6 +71,10 @@ class amg_options(Structure):
         ("graphs", c_int32),
         ("jacobi_omega", c_double),
         ("simple_alpha", c_double),
+        ("prolongator", c_int32),
+        ("schur", c_int32),
+        ("schur_sweeps", c_int32),
+        ("sa_omega", c_double),
     ]
 
 
@@ -195,6 +199,10 @@ class AMGOptions:
     graphs: int = 1  # replay the V-cycle from a captured HIP graph
     jacobi_omega: float = 0.8
     simple_alpha: float = 0.8
+    prolongator: int = 0  # 0 tentative, 1 smoothed aggregation (displacement transfers)
+    schur: int = 0  # Schur diagonal: 0 diag(S), 1 signed l1 row sums
+    schur_sweeps: int = 1  # Jacobi sweeps on the Schur system (1 = division by the diagonal)
+    sa_omega: float = 4.0 / 3.0
 
     def to_c(self) -> amg_options:
         o = amg_options()
@@ -311,10 +319,11 @@ class AMGSolver:
         return du, dl
 
     def level_matrix(self, level: int, which: str):
-        """Host copy of block K/G/B/C/P_u/P_l of a level as scipy CSR."""
+        """Host copy of block K/G/B/C/P_u/P_l/S of a level as scipy CSR (S:
+        the Schur matrix, kept only with schur_sweeps > 1, else 0 x 0)."""
         import scipy.sparse as sp
 
-        w = {"K": 0, "G": 1, "B": 2, "C": 3, "P_u": 4, "P_l": 5}[which]
+        w = {"K": 0, "G": 1, "B": 2, "C": 3, "P_u": 4, "P_l": 5, "S": 6}[which]
         nr, nc, nz = c_int64(), c_int64(), c_int64()
         _check(self.lib.amg_get_level_matrix(self.handle, level, w, byref(nr), byref(nc), byref(nz), None, None, None))
         rp = np.zeros(nr.value + 1, np.int64)

@@ -150,7 +150,7 @@ template <typename T, int SG, bool FIRST>
 __global__ void __launch_bounds__(kBlock) k_smooth_l(DCSR<T> B, DCSR<T> C, const T* __restrict__ znu,
                                                      const T* __restrict__ zl, const T* __restrict__ bl,
                                                      const T* __restrict__ sdinv, T alpha, T* __restrict__ znl,
-                                                     T* __restrict__ delta, int n_l) {
+                                                     T* __restrict__ delta, T* __restrict__ rhs_out, int n_l) {
   const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
   const int lane = threadIdx.x % SG;
   if (row >= n_l) return;
@@ -159,7 +159,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_l(DCSR<T> B, DCSR<T> C, const
   if (!FIRST && C.nnz) s += row_dot<T, SG>(C, zl, row, lane);
   s = sg_reduce<T, SG>(s);
   if (lane == 0) {
-    const T d = -(bl[row] - s) * sdinv[row];
+    const T q = -(bl[row] - s);
+    const T d = q * sdinv[row];
+    if (rhs_out) rhs_out[row] = q;
     delta[row] = d;
     znl[row] = (FIRST ? T(0) : zl[row]) + alpha * d;
   }
@@ -200,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_tsmooth_l(DCSR<T> GT, DCSR<T> CT, co
                                                       const T* __restrict__ zl, const T* __restrict__ bl,
                                                       const T* __restrict__ su, const T* __restrict__ ainv,
                                                       const T* __restrict__ sdinv, T alpha, T* __restrict__ znl,
-                                                      T* __restrict__ delta, int n_l) {
+                                                      T* __restrict__ delta, T* __restrict__ rhs_out, int n_l) {
   const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
   const int lane = threadIdx.x % SG;
   if (row >= n_l) return;
@@ -212,7 +214,9 @@ __global__ void __launch_bounds__(kBlock) k_tsmooth_l(DCSR<T> GT, DCSR<T> CT, co
   cz = sg_reduce<T, SG>(cz);
   if (lane == 0) {
     const T sl = FIRST ? bl[row] : bl[row] - gz - cz;
-    const T d = -(sl - gs) * sdinv[row];
+    const T q = -(sl - gs);
+    const T d = q * sdinv[row];
+    if (rhs_out) rhs_out[row] = q;
     delta[row] = d;
     znl[row] = (FIRST ? T(0) : zl[row]) + alpha * d;
   }
@@ -281,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_l_first(DCSR<T> B, const T* _
                                                            const T* __restrict__ jinv, T omega,
                                                            const T* __restrict__ bl, const T* __restrict__ sdinv,
                                                            T alpha, T* __restrict__ znl, T* __restrict__ delta,
-                                                           int n_l) {
+                                                           T* __restrict__ rhs_out, int n_l) {
   const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
   const int lane = threadIdx.x % SG;
   if (row >= n_l) return;
@@ -295,9 +299,31 @@ __global__ void __launch_bounds__(kBlock) k_smooth_l_first(DCSR<T> B, const T* _
   }
   s = sg_reduce<T, SG>(s);
   if (lane == 0) {
-    const T d = -(bl[row] - s) * sdinv[row];
+    const T q = -(bl[row] - s);
+    const T d = q * sdinv[row];
+    if (rhs_out) rhs_out[row] = q;
     delta[row] = d;
     znl[row] = alpha * d;
+  }
+}
+
+// One undamped Jacobi sweep on the Schur system S delta = q:
+// d_out = d_in + sdinv .* (q - S d_in); on the last sweep also
+// zn_l = z_l + alpha * d_out (z_l null: zero).
+template <typename T, int SG>
+__global__ void __launch_bounds__(kBlock) k_schur_jacobi(DCSR<T> S, const T* __restrict__ q,
+                                                         const T* __restrict__ d_in, const T* __restrict__ sdinv,
+                                                         T* __restrict__ d_out, const T* __restrict__ zl, T alpha,
+                                                         T* __restrict__ znl, int last, int n_l) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n_l) return;
+  T s = row_dot<T, SG>(S, d_in, row, lane);
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) {
+    const T dn = d_in[row] + sdinv[row] * (q[row] - s);
+    d_out[row] = dn;
+    if (last) znl[row] = (zl ? zl[row] : T(0)) + alpha * dn;
   }
 }
 
@@ -843,15 +869,31 @@ void jacobi_extra(const DCSR<T>& M, const T* w, const T* r, const T* jinv, T ome
 
 template <typename T>
 void smooth_l(const DCSR<T>& B, const DCSR<T>& C, const T* znu, const T* zl, const T* bl, const T* sdinv, T alpha,
-              T* znl, T* delta, int n_l, bool first, hipStream_t s) {
+              T* znl, T* delta, T* rhs_out, int n_l, bool first, hipStream_t s) {
   if (n_l <= 0) return;
   constexpr int SG = 8;
   dim3 grid(grid_for(n_l, kBlock / SG));
   if (first)
-    k_smooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, n_l);
+    k_smooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, rhs_out, n_l);
   else
-    k_smooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, n_l);
+    k_smooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, rhs_out, n_l);
   CAMG_LAUNCHED();
+}
+
+template <typename T>
+T* schur_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* sdinv, const T* zl, T alpha, T* znl,
+               int steps, int n_l, int sg, hipStream_t s) {
+  if (n_l <= 0 || steps <= 0) return d_a;
+  for (int k = 0; k < steps; ++k) {
+    const int last = (k == steps - 1) ? 1 : 0;
+    CAMG_SG_DISPATCH(sg, {
+      k_schur_jacobi<T, SG><<<grid_for(n_l, kBlock / SG), kBlock, 0, s>>>(S, q, d_a, sdinv, d_b, zl, alpha, znl,
+                                                                           last, n_l);
+    });
+    CAMG_LAUNCHED();
+    std::swap(d_a, d_b);
+  }
+  return d_a;
 }
 
 template <typename T>
@@ -879,14 +921,17 @@ void tsmooth_u(const DCSR<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, c
 
 template <typename T>
 void tsmooth_l(const DCSR<T>& GT, const DCSR<T>& CT, const T* zu, const T* zl, const T* bl, const T* su,
-               const T* ainv, const T* sdinv, T alpha, T* znl, T* delta, int n_l, bool first, hipStream_t s) {
+               const T* ainv, const T* sdinv, T alpha, T* znl, T* delta, T* rhs_out, int n_l, bool first,
+               hipStream_t s) {
   if (n_l <= 0) return;
   constexpr int SG = 16;
   dim3 grid(grid_for(n_l, kBlock / SG));
   if (first)
-    k_tsmooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta, n_l);
+    k_tsmooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta, rhs_out,
+                                                     n_l);
   else
-    k_tsmooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta, n_l);
+    k_tsmooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta,
+                                                      rhs_out, n_l);
   CAMG_LAUNCHED();
 }
 
@@ -992,19 +1037,21 @@ void op_apply_copy(const DBELL<double>& K, const DCSR<double>& A12, const DCSR<d
 }
 
 template <typename T>
-void smooth_first(const DCSR<T>& B, const DCSR<T>& G, const T* bu, const T* bl, const T* jinv, const T* ainv,
-                  const T* sdinv, T omega, T alpha, T* znu, T* znl, T* delta, int n_u, int n_l, hipStream_t s) {
-  if (n_l > 0) {
-    constexpr int SG = 8;
-    k_smooth_l_first<T, SG><<<grid_for(n_l, kBlock / SG), kBlock, 0, s>>>(B, bu, jinv, omega, bl, sdinv, alpha,
-                                                                          znl, delta, n_l);
-    CAMG_LAUNCHED();
-  }
-  if (n_u > 0) {
-    k_smooth_u_first_corr<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(G, bu, jinv, omega, delta, ainv, alpha, znu,
-                                                                       n_u);
-    CAMG_LAUNCHED();
-  }
+void smooth_first_l(const DCSR<T>& B, const T* bu, const T* bl, const T* jinv, const T* sdinv, T omega, T alpha,
+                    T* znl, T* delta, T* rhs_out, int n_l, hipStream_t s) {
+  if (n_l <= 0) return;
+  constexpr int SG = 8;
+  k_smooth_l_first<T, SG><<<grid_for(n_l, kBlock / SG), kBlock, 0, s>>>(B, bu, jinv, omega, bl, sdinv, alpha, znl,
+                                                                        delta, rhs_out, n_l);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void smooth_first_u(const DCSR<T>& G, const T* bu, const T* jinv, const T* ainv, const T* delta, T omega, T alpha,
+                    T* znu, int n_u, hipStream_t s) {
+  if (n_u <= 0) return;
+  k_smooth_u_first_corr<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(G, bu, jinv, omega, delta, ainv, alpha, znu, n_u);
+  CAMG_LAUNCHED();
 }
 
 template <typename T>
@@ -1173,21 +1220,25 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
                             int, bool, int, hipStream_t);                                                          \
   template void jacobi_extra<T>(const DCSR<T>&, const T*, const T*, const T*, T, T*, const T*, T*, bool, int, int, \
                                 hipStream_t);                                                                      \
-  template void smooth_l<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T, T*, T*, int, \
-                            bool, hipStream_t);                                                                    \
+  template void smooth_l<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T, T*, T*, T*, \
+                            int, bool, hipStream_t);                                                               \
+  template T* schur_steps<T>(const DCSR<T>&, const T*, T*, T*, const T*, const T*, T, T*, int, int, int,          \
+                             hipStream_t);                                                                         \
   template void correct_u<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, hipStream_t);         \
   template void tsmooth_u<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, T*, int, bool, int,      \
                              hipStream_t);                                                                         \
   template void tsmooth_l<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, const T*,      \
-                             const T*, T, T*, T*, int, bool, hipStream_t);                                         \
+                             const T*, T, T*, T*, T*, int, bool, hipStream_t);                                     \
   template void tcorrect_u<T>(const DCSR<T>&, const T*, const T*, const T*, T, T, const T*, T*, T*, T*, int, bool,  \
                               hipStream_t);                                                                        \
   template void dense_gemv<T>(const T*, const T*, T*, int, hipStream_t);                                           \
   template void copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                                   \
   template void zero_vec<T>(T*, int64_t, hipStream_t);                                                             \
   template void scatter_perm<T>(const double*, const int32_t*, T*, int64_t, hipStream_t);                          \
-  template void smooth_first<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, const T*,  \
-                                T, T, T*, T*, T*, int, int, hipStream_t);                                          \
+  template void smooth_first_l<T>(const DCSR<T>&, const T*, const T*, const T*, const T*, T, T, T*, T*, T*, int,   \
+                                  hipStream_t);                                                                    \
+  template void smooth_first_u<T>(const DCSR<T>&, const T*, const T*, const T*, const T*, T, T, T*, int,          \
+                                  hipStream_t);                                                                    \
   template void blk_spmv_bell<T>(const DBELL<T>&, const DCSR<T>&, const DCSR<T>&, const DCSR<T>&, const T*,        \
                                  const T*, const T*, const T*, T*, T*, int, int, int, hipStream_t);               \
   template void smooth_u_bell<T>(const DBELL<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T, T*,   \

@@ -29,11 +29,15 @@ void smooth_u(const DCSR<T>& K, const DCSR<T>& G, const T* zu, const T* zl, cons
               T* znu, T* r_out, T* w_out, int n_u, bool first, int sg, hipStream_t s);
 
 // First forward sweep from z = 0 (one Jacobi sweep) in two kernels:
-// delta = -(b_l - B (omega*jinv.*b_u)) .* sdinv, zn_l = alpha*delta, then
-// zn_u = omega*jinv.*b_u - alpha*ainv.*(G delta).  delta needs n_l >= 1 entries.
+// smooth_first_l: q = -(b_l - B (omega*jinv.*b_u)), delta = q .* sdinv,
+// zn_l = alpha*delta (q stored in rhs_out when non-null); then, after any
+// Schur sweeps, smooth_first_u: zn_u = omega*jinv.*b_u - alpha*ainv.*(G delta).
 template <typename T>
-void smooth_first(const DCSR<T>& B, const DCSR<T>& G, const T* bu, const T* bl, const T* jinv, const T* ainv,
-                  const T* sdinv, T omega, T alpha, T* znu, T* znl, T* delta, int n_u, int n_l, hipStream_t s);
+void smooth_first_l(const DCSR<T>& B, const T* bu, const T* bl, const T* jinv, const T* sdinv, T omega, T alpha,
+                    T* znl, T* delta, T* rhs_out, int n_l, hipStream_t s);
+template <typename T>
+void smooth_first_u(const DCSR<T>& G, const T* bu, const T* jinv, const T* ainv, const T* delta, T omega, T alpha,
+                    T* znu, int n_u, hipStream_t s);
 
 // Extra damped-Jacobi sweep on M w = r: w_out = w + omega*jinv*(r - M w);
 // when last, also zn_u = z_u + w_out (z_u null: zn_u = w_out).
@@ -43,9 +47,18 @@ void jacobi_extra(const DCSR<T>& M, const T* w, const T* r, const T* jinv, T ome
 
 // CheapSIMPLE forward sweep, multiplier rows: rt = b_l - B zn_u - C z_l,
 // delta = -rt * sdinv, zn_l = z_l + alpha * delta.  first: z_l = 0.
+// rhs_out (optional) receives q = -rt, the right-hand side of S delta = q.
 template <typename T>
 void smooth_l(const DCSR<T>& B, const DCSR<T>& C, const T* znu, const T* zl, const T* bl, const T* sdinv, T alpha,
-              T* znl, T* delta, int n_l, bool first, hipStream_t s);
+              T* znl, T* delta, T* rhs_out, int n_l, bool first, hipStream_t s);
+
+// `steps` undamped Jacobi sweeps on S delta = q continuing from d_a (the
+// first sweep's delta = q .* sdinv), ping-ponging between d_a and d_b; the
+// last one also writes zn_l = z_l + alpha * delta (z_l null: zero).
+// Returns the buffer holding the final delta.
+template <typename T>
+T* schur_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* sdinv, const T* zl, T alpha, T* znl,
+               int steps, int n_l, int sg, hipStream_t s);
 
 // zn_u[i] -= alpha * ainv[i] * (G delta)[i] for the listed rows of G.
 template <typename T>
@@ -58,10 +71,12 @@ void tsmooth_u(const DCSR<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, c
                bool first, int sg, hipStream_t s);
 
 // Adjoint sweep, step 2: s_l = b_l - G^T z_u - C^T z_l,
-// delta = -(s_l - G^T (ainv .* s_u)) * sdinv, zn_l = z_l + alpha * delta.
+// delta = -(s_l - G^T (ainv .* s_u)) * sdinv, zn_l = z_l + alpha * delta;
+// rhs_out (optional) receives q = -(s_l - G^T (ainv .* s_u)).
 template <typename T>
 void tsmooth_l(const DCSR<T>& GT, const DCSR<T>& CT, const T* zu, const T* zl, const T* bl, const T* su,
-               const T* ainv, const T* sdinv, T alpha, T* znl, T* delta, int n_l, bool first, hipStream_t s);
+               const T* ainv, const T* sdinv, T alpha, T* znl, T* delta, T* rhs_out, int n_l, bool first,
+               hipStream_t s);
 
 // Adjoint sweep, step 3: t = s_u - alpha * B^T delta, w = omega*jinv*t,
 // zn_u = z_u + w (first: z_u = 0).  t_out / w_out optional.

@@ -24,17 +24,96 @@
 //    is one constant per Cartesian component.
 //  * Galerkin blocks on the symbolic pattern of R A P (no dropping).
 //  * Coarse interface nodes: aggregates containing interface nodes.
+//  * Optional smoothed aggregation (Sec. 3.1.2, prolongator smoothing):
+//    P = P_tent - omega Atilde^-1 K P_tent with the lumped diagonal
+//    Atilde = diag(sum_j |K_ij|), whose bound lambda(Atilde^-1 K) <= 1 lets
+//    the printed omega = 4/3 be used as is; pattern = P_tent's plus the
+//    symbolic pattern of K P_tent.
+//  * Optional Schur sweeps: S = B Atilde^-1 G - C on the symbolic pattern of
+//    B G plus C's, diagonal either S_jj or sign(S_jj) sum_k |S_jk|.
 #include "setup.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
+#include <thread>
 
 namespace camg {
 
 namespace {
 
 [[noreturn]] void fail(int code, const std::string& m) { throw SetupError{code, m}; }
+
+// Host threads for the row-independent products: OMP_NUM_THREADS when set
+// (the process's CPU share), else the hardware count, at most 64.
+int setup_threads() {
+  int n = 0;
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) n = std::atoi(e);
+  if (n <= 0) n = (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(n, 64));
+}
+
+// Runs body(c, t) for every chunk c in [0, n_chunks) on nt threads (t is
+// the thread's index in [0, nt), for per-thread scratch), chunks handed out
+// in increasing order.  Results must depend only on the chunk, never on the
+// thread, so the output is identical for any thread count.  The first
+// exception thrown by a body is rethrown after all threads end.
+template <typename Body>
+void parallel_chunks(int64_t n_chunks, int nt, Body body) {
+  if (nt <= 1) {
+    for (int64_t c = 0; c < n_chunks; ++c) body(c, 0);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::exception_ptr err;
+  std::atomic<bool> failed{false};
+  auto work = [&](int t) {
+    for (;;) {
+      const int64_t c = next.fetch_add(1);
+      if (c >= n_chunks || failed.load()) return;
+      try {
+        body(c, t);
+      } catch (...) {
+        if (!failed.exchange(true)) err = std::current_exception();
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& t : pool) t.join();
+  if (err) std::rethrow_exception(err);
+}
+
+// Rows [r0, r1) of a CSR result computed by one chunk.
+struct RowBlock {
+  std::vector<int64_t> len;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+};
+
+// Concatenates per-chunk row blocks (in chunk order) into out.
+void append_blocks(HostCSR& out, std::vector<RowBlock>& blocks) {
+  int64_t total = 0;
+  for (auto& b : blocks) total += (int64_t)b.ci.size();
+  out.ci.reserve((size_t)total);
+  out.v.reserve((size_t)total);
+  int64_t r = 0;
+  for (auto& b : blocks) {
+    for (int64_t l : b.len) {
+      out.rp[r + 1] = out.rp[r] + l;
+      ++r;
+    }
+    out.ci.insert(out.ci.end(), b.ci.begin(), b.ci.end());
+    out.v.insert(out.v.end(), b.v.begin(), b.v.end());
+    RowBlock().len.swap(b.len);
+    std::vector<int32_t>().swap(b.ci);
+    std::vector<double>().swap(b.v);
+  }
+}
 
 constexpr int kErrZeroDiag = -4;
 constexpr int kErrRankDeficient = -5;
@@ -239,64 +318,167 @@ void tentative(int64_t n_rows, int n_ns, const std::vector<double>& ns, const st
 }
 
 // R A P on the symbolic pattern.  Consecutive rows of R with identical
-// column sets (the rows of one aggregate) share one pass over A P.
+// column sets (the rows of one aggregate) share one pass over A P; groups
+// are independent and run on the setup threads.
 HostCSR galerkin(const HostCSR& R, const HostCSR& A, const HostCSR& P) {
   HostCSR out;
   out.init_empty(R.nrows, P.ncols);
-  std::vector<int32_t> loc((size_t)P.ncols, -1);
-  std::vector<int32_t> touched;
-  std::vector<int32_t> fine;
-  std::vector<double> tmp;  // fine.size() x touched.size()
-  int64_t r0 = 0;
-  while (r0 < R.nrows) {
-    int64_t r1 = r0 + 1;
-    auto same = [&](int64_t a, int64_t b) {
-      int64_t la = R.rp[a + 1] - R.rp[a], lb = R.rp[b + 1] - R.rp[b];
-      if (la != lb) return false;
-      return std::equal(R.ci.begin() + R.rp[a], R.ci.begin() + R.rp[a + 1], R.ci.begin() + R.rp[b]);
-    };
-    while (r1 < R.nrows && same(r0, r1)) ++r1;
-    fine.assign(R.ci.begin() + R.rp[r0], R.ci.begin() + R.rp[r0 + 1]);
-    touched.clear();
-    for (int32_t i : fine)
-      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-        int32_t j = A.ci[k];
-        for (int64_t q = P.rp[j]; q < P.rp[j + 1]; ++q) {
-          int32_t c = P.ci[q];
-          if (loc[c] < 0) {
-            loc[c] = (int32_t)touched.size();
-            touched.push_back(c);
+  auto same = [&](int64_t a, int64_t b) {
+    int64_t la = R.rp[a + 1] - R.rp[a], lb = R.rp[b + 1] - R.rp[b];
+    if (la != lb) return false;
+    return std::equal(R.ci.begin() + R.rp[a], R.ci.begin() + R.rp[a + 1], R.ci.begin() + R.rp[b]);
+  };
+  std::vector<int64_t> gstart;  // first row of each group, plus R.nrows
+  for (int64_t r = 0; r < R.nrows; ++r)
+    if (r == 0 || !same(r - 1, r)) gstart.push_back(r);
+  gstart.push_back(R.nrows);
+  const int64_t n_groups = (int64_t)gstart.size() - 1;
+  constexpr int64_t kGroupsPerChunk = 64;
+  const int64_t n_chunks = (n_groups + kGroupsPerChunk - 1) / kGroupsPerChunk;
+  std::vector<RowBlock> blocks((size_t)n_chunks);
+  const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n_chunks, 1));
+  std::vector<std::vector<int32_t>> locs((size_t)nt);
+  parallel_chunks(n_chunks, nt, [&](int64_t c, int t) {
+    std::vector<int32_t>& loc = locs[(size_t)t];
+    if (loc.empty()) loc.assign((size_t)P.ncols, -1);
+    std::vector<int32_t> touched, fine;
+    std::vector<double> tmp;  // fine.size() x touched.size()
+    RowBlock& blk = blocks[(size_t)c];
+    const int64_t g1 = std::min(n_groups, (c + 1) * kGroupsPerChunk);
+    for (int64_t g = c * kGroupsPerChunk; g < g1; ++g) {
+      const int64_t r0 = gstart[(size_t)g], r1 = gstart[(size_t)g + 1];
+      fine.assign(R.ci.begin() + R.rp[r0], R.ci.begin() + R.rp[r0 + 1]);
+      touched.clear();
+      for (int32_t i : fine)
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+          int32_t j = A.ci[k];
+          for (int64_t q = P.rp[j]; q < P.rp[j + 1]; ++q) {
+            int32_t col = P.ci[q];
+            if (loc[col] < 0) {
+              loc[col] = (int32_t)touched.size();
+              touched.push_back(col);
+            }
           }
         }
+      std::sort(touched.begin(), touched.end());
+      for (size_t t = 0; t < touched.size(); ++t) loc[touched[t]] = (int32_t)t;
+      const size_t ntc = touched.size();
+      tmp.assign(fine.size() * ntc, 0.0);
+      for (size_t f = 0; f < fine.size(); ++f) {
+        int32_t i = fine[f];
+        double* trow = tmp.data() + f * ntc;
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+          int32_t j = A.ci[k];
+          double a = A.v[k];
+          for (int64_t q = P.rp[j]; q < P.rp[j + 1]; ++q) trow[loc[P.ci[q]]] += a * P.v[q];
+        }
       }
-    std::sort(touched.begin(), touched.end());
-    for (size_t t = 0; t < touched.size(); ++t) loc[touched[t]] = (int32_t)t;
-    const size_t nt = touched.size();
-    tmp.assign(fine.size() * nt, 0.0);
-    for (size_t f = 0; f < fine.size(); ++f) {
-      int32_t i = fine[f];
-      double* trow = tmp.data() + f * nt;
-      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-        int32_t j = A.ci[k];
-        double a = A.v[k];
-        for (int64_t q = P.rp[j]; q < P.rp[j + 1]; ++q) trow[loc[P.ci[q]]] += a * P.v[q];
+      for (int64_t r = r0; r < r1; ++r) {
+        size_t base = blk.ci.size();
+        blk.ci.insert(blk.ci.end(), touched.begin(), touched.end());
+        blk.v.resize(base + ntc, 0.0);
+        double* orow = blk.v.data() + base;
+        int64_t f = 0;
+        for (int64_t k = R.rp[r]; k < R.rp[r + 1]; ++k, ++f) {
+          double w = R.v[k];
+          const double* trow = tmp.data() + (size_t)f * ntc;
+          for (size_t t = 0; t < ntc; ++t) orow[t] += w * trow[t];
+        }
+        blk.len.push_back((int64_t)ntc);
       }
+      for (int32_t col : touched) loc[col] = -1;
     }
-    for (int64_t r = r0; r < r1; ++r) {
-      size_t base = out.ci.size();
-      out.ci.insert(out.ci.end(), touched.begin(), touched.end());
-      out.v.resize(base + nt, 0.0);
-      double* orow = out.v.data() + base;
-      int64_t f = 0;
-      for (int64_t k = R.rp[r]; k < R.rp[r + 1]; ++k, ++f) {
-        double w = R.v[k];
-        const double* trow = tmp.data() + (size_t)f * nt;
-        for (size_t t = 0; t < nt; ++t) orow[t] += w * trow[t];
-      }
-      out.rp[r + 1] = out.nnz();
+  });
+  append_blocks(out, blocks);
+  return out;
+}
+
+// Sorted union of the column patterns gathered by `visit`, with loc[] set to
+// each column's position; returns the count.  loc must be all -1 on entry.
+template <typename Visit>
+size_t gather_pattern(std::vector<int32_t>& cols, std::vector<int32_t>& loc, Visit visit) {
+  cols.clear();
+  visit([&](int32_t c) {
+    if (loc[c] < 0) {
+      loc[c] = 0;
+      cols.push_back(c);
     }
-    for (int32_t c : touched) loc[c] = -1;
-    r0 = r1;
+  });
+  std::sort(cols.begin(), cols.end());
+  for (size_t t = 0; t < cols.size(); ++t) loc[cols[t]] = (int32_t)t;
+  return cols.size();
+}
+
+HostCSR smooth_prolongator(const HostCSR& K, const HostCSR& Pt, double omega) {
+  HostCSR out;
+  out.init_empty(K.nrows, Pt.ncols);
+  constexpr int64_t kRowsPerChunk = 4096;
+  const int64_t n_chunks = (K.nrows + kRowsPerChunk - 1) / kRowsPerChunk;
+  std::vector<RowBlock> blocks((size_t)n_chunks);
+  const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n_chunks, 1));
+  std::vector<std::vector<int32_t>> locs((size_t)nt);
+  parallel_chunks(n_chunks, nt, [&](int64_t c, int t) {
+    std::vector<int32_t>& loc = locs[(size_t)t];
+    if (loc.empty()) loc.assign((size_t)Pt.ncols, -1);
+    std::vector<int32_t> cols;
+    std::vector<double> acc, ph;
+    RowBlock& blk = blocks[(size_t)c];
+    const int64_t i1 = std::min(K.nrows, (c + 1) * kRowsPerChunk);
+    for (int64_t i = c * kRowsPerChunk; i < i1; ++i) {
+      const size_t nc = gather_pattern(cols, loc, [&](auto add) {
+        for (int64_t q = Pt.rp[i]; q < Pt.rp[i + 1]; ++q) add(Pt.ci[q]);
+        for (int64_t k = K.rp[i]; k < K.rp[i + 1]; ++k)
+          for (int64_t q = Pt.rp[K.ci[k]]; q < Pt.rp[K.ci[k] + 1]; ++q) add(Pt.ci[q]);
+      });
+      acc.assign(nc, 0.0);
+      ph.assign(nc, 0.0);
+      double rs = 0.0;
+      for (int64_t k = K.rp[i]; k < K.rp[i + 1]; ++k) {
+        const double a = K.v[k];
+        rs += std::fabs(a);
+        const int32_t j = K.ci[k];
+        for (int64_t q = Pt.rp[j]; q < Pt.rp[j + 1]; ++q) acc[(size_t)loc[Pt.ci[q]]] += a * Pt.v[q];
+      }
+      for (int64_t q = Pt.rp[i]; q < Pt.rp[i + 1]; ++q) ph[(size_t)loc[Pt.ci[q]]] = Pt.v[q];
+      if (rs == 0.0) fail(kErrZeroDiag, "zero row of K in prolongator smoothing");
+      const double w = omega / rs;
+      for (size_t t = 0; t < nc; ++t) {
+        blk.ci.push_back(cols[t]);
+        blk.v.push_back(ph[t] - w * acc[t]);
+        loc[cols[t]] = -1;
+      }
+      blk.len.push_back((int64_t)nc);
+    }
+  });
+  append_blocks(out, blocks);
+  return out;
+}
+
+HostCSR schur_matrix(const HostLevel& L) {
+  const int64_t nl = L.n_l();
+  HostCSR out;
+  out.init_empty(nl, nl);
+  std::vector<int32_t> loc((size_t)nl, -1), cols;
+  std::vector<double> acc;
+  for (int64_t j = 0; j < nl; ++j) {
+    const size_t nc = gather_pattern(cols, loc, [&](auto add) {
+      for (int64_t k = L.B.rp[j]; k < L.B.rp[j + 1]; ++k)
+        for (int64_t q = L.G.rp[L.B.ci[k]]; q < L.G.rp[L.B.ci[k] + 1]; ++q) add(L.G.ci[q]);
+      for (int64_t q = L.C.rp[j]; q < L.C.rp[j + 1]; ++q) add(L.C.ci[q]);
+    });
+    acc.assign(nc, 0.0);
+    for (int64_t k = L.B.rp[j]; k < L.B.rp[j + 1]; ++k) {
+      const int32_t i = L.B.ci[k];
+      const double bk = L.B.v[k] * L.atilde_inv[i];
+      for (int64_t q = L.G.rp[i]; q < L.G.rp[i + 1]; ++q) acc[(size_t)loc[L.G.ci[q]]] += bk * L.G.v[q];
+    }
+    for (int64_t q = L.C.rp[j]; q < L.C.rp[j + 1]; ++q) acc[(size_t)loc[L.C.ci[q]]] -= L.C.v[q];
+    for (size_t t = 0; t < nc; ++t) {
+      out.ci.push_back(cols[t]);
+      out.v.push_back(acc[t]);
+      loc[cols[t]] = -1;
+    }
+    out.rp[j + 1] = out.nnz();
   }
   return out;
 }
@@ -321,8 +503,23 @@ void smoother_data(HostLevel& L, const SetupOptions& opt) {
     L.atilde_inv[i] = 1.0 / a;
     L.jac_inv[i] = opt.jacobi_diag == 0 ? 1.0 / a : 1.0 / dg[i];
   }
-  // S_d[j] = sum_i B[j,i] G[i,j] / Atilde_i - C[j,j]
   L.sd_inv.resize((size_t)nl);
+  if (opt.schur == 1 || opt.schur_sweeps > 1) {
+    HostCSR S = schur_matrix(L);
+    for (int64_t j = 0; j < nl; ++j) {
+      double d = 0.0, l1 = 0.0;
+      for (int64_t k = S.rp[j]; k < S.rp[j + 1]; ++k) {
+        l1 += std::fabs(S.v[k]);
+        if (S.ci[k] == j) d = S.v[k];
+      }
+      const double sd = opt.schur == 1 ? (d > 0.0 ? l1 : (d < 0.0 ? -l1 : 0.0)) : d;
+      if (sd == 0.0) fail(kErrZeroDiag, "zero diagonal of the Schur approximation");
+      L.sd_inv[j] = 1.0 / sd;
+    }
+    if (opt.schur_sweeps > 1) L.S = std::move(S);
+    return;
+  }
+  // S_d[j] = sum_i B[j,i] G[i,j] / Atilde_i - C[j,j]
   for (int64_t j = 0; j < nl; ++j) {
     double s = 0.0;
     for (int64_t k = L.B.rp[j]; k < L.B.rp[j + 1]; ++k) {
@@ -402,7 +599,7 @@ void coarse_inverse(HostLevel& L) {
   }
 }
 
-HostLevel coarsen(HostLevel& L) {
+HostLevel coarsen(HostLevel& L, const SetupOptions& opt) {
   const int bs = L.bs_u;
   const int64_t nn = L.n_u() / bs;
   L.dirichlet = find_dirichlet(L.K, L.G);
@@ -424,6 +621,7 @@ HostLevel coarsen(HostLevel& L) {
   tentative(
       L.n_l(), L.n_ns_l, L.ns_l, L.agg_l, L.n_agg_l, [&](int64_t r) { return (int64_t)L.lm_node[r]; },
       [&](int64_t) { return false; }, L.P_l, nsc_l);
+  if (opt.prolongator == 1) L.P_u = smooth_prolongator(L.K, L.P_u, opt.sa_omega);
   HostCSR Ru = transpose(L.P_u), Rl = transpose(L.P_l);
   Cn.K = galerkin(Ru, L.K, L.P_u);
   Cn.G = galerkin(Ru, L.G, L.P_l);
@@ -472,7 +670,7 @@ HostCSR transpose(const HostCSR& A, std::vector<int32_t>* perm) {
 
 void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt) {
   while ((int)levels.size() < opt.max_levels && levels.back().n() > opt.max_coarse_rows) {
-    HostLevel nxt = coarsen(levels.back());
+    HostLevel nxt = coarsen(levels.back(), opt);
     if (nxt.n() >= levels.back().n()) {
       // no coarsening progress: drop the aggregation data of the last level
       HostLevel& L = levels.back();

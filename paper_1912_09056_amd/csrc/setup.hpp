@@ -41,6 +41,7 @@ struct HostLevel {
   int64_t n_agg_u = 0, n_agg_l = 0;
   HostCSR P_u, P_l;
   std::vector<double> atilde_inv, jac_inv, sd_inv;
+  HostCSR S;                       // B Atilde^-1 G - C (only when relaxed by Jacobi sweeps)
   std::vector<double> Ainv;        // coarsest level: dense inverse, row-major
   int64_t n_u() const { return K.nrows; }
   int64_t n_l() const { return C.nrows; }
@@ -53,6 +54,10 @@ struct SetupOptions {
   int max_coarse_rows = 1000;
   int atilde = 0;       // 0 row sums of |K|, 1 diag(K)
   int jacobi_diag = 0;  // 0 Atilde, 1 diag(K)
+  int prolongator = 0;  // 0 tentative, 1 smoothed (displacement transfers)
+  double sa_omega = 4.0 / 3.0;
+  int schur = 0;         // 0 diagonal of S, 1 signed l1 row sums of S
+  int schur_sweeps = 1;  // > 1: keep S for Jacobi sweeps
 };
 
 // Status codes mirror the C-ABI's CAMG_* values.

@@ -184,6 +184,7 @@ static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipSt
 template <typename T>
 struct LevelVecs {
   DBuf<T> b, z, zn, r, delta, aux1, aux2, su;
+  DBuf<T> delta2, qrhs;  // Schur sweeps: second delta buffer and right-hand side
   DBuf<T> jinv, ainv, sdinv;
   DBuf<T> Ainv, AinvT;
 };
@@ -191,6 +192,8 @@ struct LevelVecs {
 struct DevLevel {
   int64_t n_u = 0, n_l = 0;
   DevMat K, G, B, C, KT, GT, BT, CT, Pu, Pl, Ru, Rl;
+  DevMat S, ST;  // Schur matrix B Atilde^-1 G - C and its transpose (Schur sweeps only)
+  int sg_S = 8;
   bool bell = false;   // K and K^T in sliced blocked-ELL layout
   DevBell Kb, KTb;
   int64_t k_blocks = 0, k_slots = 0;
@@ -329,8 +332,10 @@ static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool coarsest, hipSt
     b->alloc((size_t)n);
     zero_vec<T>(b->p, n, s);
   }
-  V.delta.alloc((size_t)std::max<int64_t>(nl, 1));
-  zero_vec<T>(V.delta.p, std::max<int64_t>(nl, 1), s);
+  for (DBuf<T>* b : {&V.delta, &V.delta2, &V.qrhs}) {
+    b->alloc((size_t)std::max<int64_t>(nl, 1));
+    zero_vec<T>(b->p, std::max<int64_t>(nl, 1), s);
+  }
   for (DBuf<T>* b : {&V.aux1, &V.aux2, &V.su}) {
     b->alloc((size_t)std::max<int64_t>(nu, 1));
     zero_vec<T>(b->p, std::max<int64_t>(nu, 1), s);
@@ -408,6 +413,11 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       upload_mat(D.Rl, Rl, t64, f32, s);
       D.sg_R = pick_subgroup(Ru.nnz(), Ru.nrows);
       D.sg_P = pick_subgroup(H.P_u.nnz(), H.P_u.nrows);
+      if (H.S.nrows > 0) {
+        upload_mat(D.S, H.S, t64, f32, s);
+        upload_mat(D.ST, transpose(H.S), t64, f32, s);
+        D.sg_S = pick_subgroup(H.S.nnz(), H.S.nrows);
+      }
       std::vector<int32_t> gr;
       for (int64_t i = 0; i < H.G.nrows; ++i)
         if (H.G.rp[i + 1] > H.G.rp[i]) gr.push_back((int32_t)i);
@@ -449,6 +459,8 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   const int nu = (int)D.n_u, nl = (int)D.n_l;
   const T om = (T)h.opts.jacobi_omega, al = (T)h.opts.simple_alpha;
   const int nj = std::max(1, h.opts.jacobi_sweeps);
+  const int ks = D.S.nrows > 0 ? std::max(1, h.opts.schur_sweeps) - 1 : 0;  // Jacobi sweeps on S after the first
+  T* q = ks ? V.qrhs.p : nullptr;
   const T* bu = b;
   const T* bl = b + nu;
   const T* zu = z;
@@ -457,8 +469,10 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   T* znl = zn + nu;
   Prof* pp = (l == 0) ? &h.prof : nullptr;
   if (!transpose && first && nj == 1) {
-    smooth_first<T>(D.B.view<T>(), D.G.view<T>(), bu, bl, V.jinv.p, V.ainv.p, V.sdinv.p, om, al, znu, znl,
-                    V.delta.p, nu, nl, s);
+    smooth_first_l<T>(D.B.view<T>(), bu, bl, V.jinv.p, V.sdinv.p, om, al, znl, V.delta.p, q, nl, s);
+    const T* dfin = schur_steps<T>(D.S.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, nullptr, al, znl, ks, nl,
+                                   D.sg_S, s);
+    smooth_first_u<T>(D.G.view<T>(), bu, V.jinv.p, V.ainv.p, dfin, om, al, znu, nu, s);
     return;
   }
   if (!transpose) {
@@ -482,8 +496,10 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
                         D.sg_K, s);
       std::swap(wa, wb);
     }
-    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, V.sdinv.p, al, znl, V.delta.p, nl, first, s);
-    correct_u<T>(D.G.view<T>(), D.g_rows.p, D.n_g_rows, V.delta.p, V.ainv.p, al, znu, s);
+    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, V.sdinv.p, al, znl, V.delta.p, q, nl, first, s);
+    const T* dfin = schur_steps<T>(D.S.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, first ? nullptr : zl, al,
+                                   znl, ks, nl, D.sg_S, s);
+    correct_u<T>(D.G.view<T>(), D.g_rows.p, D.n_g_rows, dfin, V.ainv.p, al, znu, s);
   } else {
     // from z = 0 the adjoint residual is b itself: no first kernel
     const T* su = first ? bu : V.su.p;
@@ -494,9 +510,11 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
       else
         tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, false, D.sg_K, s);
     }
-    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, su, V.ainv.p, V.sdinv.p, al, znl, V.delta.p, nl, first,
-                 s);
-    tcorrect_u<T>(D.BT.view<T>(), su, V.delta.p, V.jinv.p, om, al, zu, znu, nj > 1 ? V.aux1.p : nullptr,
+    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, su, V.ainv.p, V.sdinv.p, al, znl, V.delta.p, q, nl,
+                 first, s);
+    const T* dfin = schur_steps<T>(D.ST.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, first ? nullptr : zl, al,
+                                   znl, ks, nl, D.sg_S, s);
+    tcorrect_u<T>(D.BT.view<T>(), su, dfin, V.jinv.p, om, al, zu, znu, nj > 1 ? V.aux1.p : nullptr,
                   nj > 1 ? V.aux2.p : nullptr, nu, first, s);
     T* wa = V.aux2.p;
     T* wb = V.r.p;  // r is free during a sweep
@@ -868,6 +886,10 @@ void amg_default_options(amg_options* o) {
   o->graphs = 1;
   o->jacobi_omega = 0.8;
   o->simple_alpha = 0.8;
+  o->prolongator = CAMG_PROLONG_TENTATIVE;
+  o->schur = CAMG_SCHUR_DIAG;
+  o->schur_sweeps = 1;
+  o->sa_omega = 4.0 / 3.0;
 }
 
 void amg_default_gmres_options(amg_gmres_options* o) {
@@ -892,7 +914,8 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
       (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 1 ||
       o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
-      o.graphs > 1)
+      o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 1 || o.schur_sweeps < 1 ||
+      o.schur_sweeps > 64 || !(o.sa_omega > 0.0) || !std::isfinite(o.sa_omega))
     api_fail(CAMG_ERR_INVALID_ARG, "invalid options");
   const int64_t nu = p->K.nrows, nl = p->C.nrows;
   if (nu <= 0 || nu % p->dim) api_fail(CAMG_ERR_SHAPE, "n_u must be a positive multiple of dim");
@@ -958,6 +981,10 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   so.max_coarse_rows = o.max_coarse_rows;
   so.atilde = o.atilde;
   so.jacobi_diag = o.jacobi_diag;
+  so.prolongator = o.prolongator;
+  so.sa_omega = o.sa_omega;
+  so.schur = o.schur;
+  so.schur_sweeps = o.schur_sweeps;
   build_hierarchy(h->host, so);
   return h;
 }
@@ -1044,16 +1071,20 @@ int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_
 int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols, int64_t* nnz,
                          int64_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> int {
-    if (!h || level < 0 || level >= (int)h->host.size() || which < 0 || which > 5)
+    if (!h || level < 0 || level >= (int)h->host.size() || which < 0 || which > 6)
       api_fail(CAMG_ERR_INVALID_ARG, "level/which");
     const HostLevel& L = h->host[level];
-    const HostCSR* M[6] = {&L.K, &L.G, &L.B, &L.C, &L.P_u, &L.P_l};
-    if (which >= 4 && level + 1 >= (int)h->host.size()) api_fail(CAMG_ERR_INVALID_ARG, "no transfer on coarsest");
+    const HostCSR* M[7] = {&L.K, &L.G, &L.B, &L.C, &L.P_u, &L.P_l, &L.S};
+    if ((which == 4 || which == 5) && level + 1 >= (int)h->host.size())
+      api_fail(CAMG_ERR_INVALID_ARG, "no transfer on coarsest");
     const HostCSR& A = *M[which];
     if (nrows) *nrows = A.nrows;
     if (ncols) *ncols = A.ncols;
     if (nnz) *nnz = A.nnz();
-    if (rowptr) std::copy(A.rp.begin(), A.rp.end(), rowptr);
+    if (rowptr) {
+      if (A.rp.empty()) rowptr[0] = 0;
+      else std::copy(A.rp.begin(), A.rp.end(), rowptr);
+    }
     if (col) std::copy(A.ci.begin(), A.ci.end(), col);
     if (val) std::copy(A.v.begin(), A.v.end(), val);
     return CAMG_OK;

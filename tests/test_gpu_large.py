@@ -2,7 +2,8 @@
 
 The 40^3 / 41x41x40 gradient check runs with every `-m gpu` invocation.
 The 100^3 and 150^3 workloads take minutes (input generation and host setup
-dominate), so they only run with CAMG_LARGE=1; at those sizes the oracle is
+dominate), so they only run with CAMG_LARGE=1; the 150^3 lognormal(0, 2)
+case uses the robustness settings.  At those sizes the oracle is
 replaced by properties that hold at any size: the true FP64 residual
 recomputed on the host, agreement of the FP64 and mixed solutions, the
 adjoint identity g.x = lam.b, and the transposed V-cycle's dot-product test.
@@ -85,7 +86,14 @@ def test_gradients_40_central_differences(prec):
     assert worst <= 1e-6, worst
 
 
-def _large_case(name, levels):
+# robustness settings for strong stiffness contrast: smoothed aggregation,
+# two l1-lumped Jacobi sweeps on the Schur system, three Jacobi sweeps in the
+# prediction (the plain settings stall on lognormal(0, 2) moduli: the
+# diagonal Schur step is not a convergent splitting there)
+ROBUST = dict(prolongator=1, schur=1, schur_sweeps=2, jacobi_sweeps=3)
+
+
+def _large_case(name, levels, **opts):
     import time
 
     t0 = time.time()
@@ -97,7 +105,7 @@ def _large_case(name, levels):
     out = {}
     for prec in (0, 1):
         t0 = time.time()
-        s = _solver(prob, precision=prec, max_levels=levels)
+        s = _solver(prob, precision=prec, max_levels=levels, **opts)
         print(f"[large] {name} prec={prec} setup {time.time() - t0:.0f}s, levels "
               f"{[s.level_info(l)['n_u'] + s.level_info(l)['n_l'] for l in range(s.n_levels)]}", flush=True)
         x, fi = s.solve(b, rtol=1e-8, max_iters=3000)
@@ -140,4 +148,4 @@ def test_large_100_lognormal():
 
 @pytest.mark.skipif(not LARGE, reason="set CAMG_LARGE=1 (input generation and setup take minutes)")
 def test_large_150_curved():
-    _large_case("contact3d_150_curved", 5)
+    _large_case("contact3d_150_curved", 5, **ROBUST)

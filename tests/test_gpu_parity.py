@@ -44,22 +44,32 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-# (workload, options, K storage on the device: 1 CSR, 2 sliced blocked-ELL)
+# robustness settings: smoothed aggregation, l1-lumped Schur sweeps, 3 Jacobi sweeps
+ROBUST_ORACLE = dict(prolongator="sa", schur="l1", schur_sweeps=3, jacobi_sweeps=3)
+ROBUST_LIB = dict(prolongator=1, schur=1, schur_sweeps=3, jacobi_sweeps=3)
+CURVED6 = dict(slave_elems=(6, 6, 6), master_elems=(7, 7, 6))
+
+# (workload, shared options, K storage on the device: 1 CSR, 2 sliced
+#  blocked-ELL, [oracle-only options, library-only options, generator overrides])
 CASES = {
     "2d-csr": ("contact2d_16", dict(max_levels=2, nu_pre=1, nu_post=1), 1),
     "2d-bell": ("contact2d_16", dict(max_levels=2, nu_pre=1, nu_post=1), 2),
     "3d6-csr": ("contact3d_6", dict(max_levels=2), 1),
     "3d6-bell": ("contact3d_6", dict(max_levels=2), 2),
+    "3d6-robust-csr": ("contact3d_6", dict(max_levels=2), 1, ROBUST_ORACLE, ROBUST_LIB, {}),
+    "curved6-robust-bell": ("contact3d_150_curved", dict(max_levels=2), 2, ROBUST_ORACLE, ROBUST_LIB, CURVED6),
 }
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
-    name, kw, fmt = CASES[request.param]
-    prob = make_workload(name)
-    lv = build_hierarchy(prob, OracleOptions(**kw))
-    print(f"[case] {name} {kw} fmt={fmt}", flush=True)
-    return prob, lv, OracleOptions(**kw), dict(kw, fmt=fmt)
+    name, kw, fmt, *extra = CASES[request.param]
+    okw, lkw, gen = extra if extra else ({}, {}, {})
+    prob = make_workload(name, **gen)
+    oopts = OracleOptions(**kw, **okw)
+    lv = build_hierarchy(prob, oopts)
+    print(f"[case] {request.param}: {name} {kw} {lkw} fmt={fmt}", flush=True)
+    return prob, lv, oopts, dict(kw, fmt=fmt, **lkw)
 
 
 def test_operator_apply(case):

@@ -131,3 +131,48 @@ def test_error_codes_from_host_setup():
     with pytest.raises(CamgError) as e:
         AMGSolver(2, K, p.G, p.B, p.C, p.slave_dofs, p.master_dofs, nullspace=p.nullspace, host_only=True)
     assert e.value.code == -3
+
+
+ROBUST_CASES = [
+    ("contact2d_16", dict(slave_elems=(24, 24), master_elems=(25, 24)), 3),
+    ("contact3d_6", {}, 2),
+    ("contact3d_150_curved", dict(slave_elems=(6, 6, 6), master_elems=(7, 7, 6)), 2),
+]
+
+
+@pytest.mark.parametrize("name,gen,levels", ROBUST_CASES, ids=[c[0] for c in ROBUST_CASES])
+def test_host_hierarchy_robust_options_match_oracle(name, gen, levels):
+    # smoothed displacement prolongator and the kept Schur matrix with its
+    # signed l1 diagonal: identical patterns, values to rounding
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
+
+    prob = make_workload(name, **gen)
+    ora = build_hierarchy(prob, OracleOptions(max_levels=levels, max_coarse_rows=50, prolongator="sa", schur="l1",
+                                              schur_sweeps=3, jacobi_sweeps=3))
+    lib = AMGSolver.from_problem(prob, AMGOptions(max_levels=levels, max_coarse_rows=50, prolongator=1, schur=1,
+                                                  schur_sweeps=3, jacobi_sweeps=3), host_only=True)
+    assert lib.n_levels == len(ora) == levels
+    for l, L in enumerate(ora):
+        blocks = ["K", "G", "B", "C"]
+        if l + 1 < len(ora):
+            blocks += ["P_u", "P_l", "S"]
+        for blk in blocks:
+            A = lib.level_matrix(l, blk)
+            R = getattr(L, blk)
+            assert np.array_equal(A.indptr, R.indptr) and np.array_equal(A.indices, R.indices), (l, blk)
+            scale = max(1.0, np.abs(R.data).max()) if R.nnz else 1.0
+            assert np.abs(A.data - R.data).max(initial=0.0) <= 1e-13 * scale, (l, blk)
+    # without Schur sweeps nothing is kept
+    lib1 = AMGSolver.from_problem(prob, AMGOptions(max_levels=2, schur=1), host_only=True)
+    assert lib1.level_matrix(0, "S").shape == (0, 0)
+
+
+def test_robust_options_validated():
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver, CamgError
+
+    p = make_workload("contact2d_16")
+    for bad in (dict(schur_sweeps=0), dict(schur_sweeps=65), dict(schur=2), dict(prolongator=2),
+                dict(sa_omega=0.0), dict(sa_omega=float("nan"))):
+        with pytest.raises(CamgError) as e:
+            AMGSolver.from_problem(p, AMGOptions(max_levels=2, **bad), host_only=True)
+        assert e.value.code == -1, bad
