@@ -130,9 +130,6 @@ def main():
         s = solvers[name]
         for _ in range(args.warmup):
             step(s)
-        torch.cuda.synchronize()
-        if name == "mixed":
-            s.profile_enable(KCLASS_SMOOTH_U)
         fwd, adj = [], []
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -144,6 +141,13 @@ def main():
         t_end = time.perf_counter()
         results[name] = dict(fwd=fwd, adj=adj, wall=(t_end - t_start) / args.steps)
         if name == "mixed":
+            # per-launch durations of the level-0 smoother kernel: hipEvents
+            # around every launch on the solver's stream during one more step
+            # of the same work (event brackets need eager launches, so the
+            # timed steps above replay the V-cycle graph instead)
+            s.profile_enable(KCLASS_SMOOTH_U)
+            step(s)
+            torch.cuda.synchronize()
             n_launch, ms = s.profile_read(KCLASS_SMOOTH_U)
             s.profile_enable(0)
             results[name]["smooth_u"] = (n_launch, ms)
@@ -216,6 +220,7 @@ def main():
             "k_slots_with_padding": info0["k_slots"],
             "avg_launch_us": avg_s * 1e6,
             "launches": n_launch,
+            "timing": "hipEvents around each launch on the solver stream, one profiled step after the timed ones",
         },
     }
 

@@ -220,7 +220,9 @@ struct Prof {
   hipEvent_t get() {
     if (pool_used == pool.size()) {
       hipEvent_t e;
-      CAMG_HIP(hipEventCreate(&e));
+      // timing only: skip the system-scope release fence, whose cache
+      // write-back would otherwise land inside the bracketed interval
+      CAMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       pool.push_back(e);
     }
     return pool[pool_used++];

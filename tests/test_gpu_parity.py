@@ -279,9 +279,11 @@ def test_three_level_2d_and_restart(fmt):
 
 @pytest.mark.parametrize("fmt", [1, 2])
 def test_jacobi_sweeps_and_diag_options(fmt):
-    prob = make_workload("contact2d_16")
-    for kw in (dict(max_levels=2, nu_pre=1, nu_post=2, jacobi_sweeps=2),
-               dict(max_levels=2, nu_pre=2, nu_post=1, jacobi_diag=1, jacobi_omega=0.5, atilde=1)):
+    # three levels, so the extra Jacobi sweeps also run on a coarse level
+    prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=9)
+    for kw in (dict(max_levels=3, max_coarse_rows=50, nu_pre=1, nu_post=2, jacobi_sweeps=2),
+               dict(max_levels=3, max_coarse_rows=50, nu_pre=2, nu_post=1, jacobi_diag=1, jacobi_omega=0.5,
+                    atilde=1)):
         okw = dict(kw)
         okw["jacobi_diag"] = "diag" if okw.get("jacobi_diag", 0) == 1 else "atilde"
         okw["atilde"] = "diag" if okw.get("atilde", 0) == 1 else "rowsum_abs"
@@ -292,6 +294,30 @@ def test_jacobi_sweeps_and_diag_options(fmt):
         for tr in (False, True):
             z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
             assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < 1e-12, (kw, tr)
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_robust_options_three_level(fmt):
+    """Smoothed aggregation, l1 Schur sweeps and three Jacobi sweeps on a
+    three-level 2D hierarchy: V-cycle and its transpose (FP64, and mixed to
+    FP32 accuracy) and fixed-iteration FGMRES against the oracle."""
+    prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=10)
+    kw = dict(max_levels=3, max_coarse_rows=50)
+    oopts = OracleOptions(**kw, **ROBUST_ORACLE)
+    lv = build_hierarchy(prob, oopts)
+    assert lv[1].S is not None
+    r = np.random.default_rng(12).standard_normal(prob.n)
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        s = _solver(prob, precision=prec, fmt=fmt, **kw, **ROBUST_LIB)
+        assert s.level_info(1)["k_layout"] == {1: 0, 2: 1}[fmt]
+        for tr in (False, True):
+            z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+            assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < tol, (prec, tr)
+    s = _solver(prob, fmt=fmt, **kw, **ROBUST_LIB)
+    for tr in (False, True):
+        ref = oracle_solve(lv, oopts, prob.b, transpose=tr, m=10, fixed_iters=25)
+        x, info = s.solve(torch.from_numpy(prob.b), transpose=tr, m=10, fixed_iters=25)
+        assert _rel(x.cpu().numpy(), ref.x) < 1e-10, tr
 
 
 def test_bench_workload_parity():
