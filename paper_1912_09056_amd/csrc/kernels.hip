@@ -40,6 +40,7 @@ template <typename T, int SG>
 __device__ __forceinline__ T row_dot(const DCSR<T>& A, const T* __restrict__ x, int row, int lane) {
   T s = T(0);
   const int e = A.rp[row + 1];
+#pragma unroll 4
   for (int k = A.rp[row] + lane; k < e; k += SG) s += A.v[k] * x[A.ci[k]];
   return s;
 }
@@ -58,6 +59,40 @@ __device__ __forceinline__ void row_dot2(const DCSR<T>& A, const T* __restrict__
     s1 += a * x[c];
     s2 += a * (d[c] * y[c]);
   }
+}
+
+// One thread's dot of a short CSR row with x (x converted to T on load).
+// The row is taken in chunks of 8: the chunk's column and value loads are
+// issued together, then its x gathers, then the products are added in
+// entry order -- the same sum as a plain loop, with a dependent-load chain
+// of 2 per chunk instead of 2 per entry.
+template <typename T, typename XT>
+__device__ __forceinline__ T csr_row_serial_x(const DCSR<T>& A, const XT* __restrict__ x, int row) {
+  constexpr int U = 8;
+  const int e = A.rp[row + 1];
+  T s = T(0);
+  for (int k0 = A.rp[row]; k0 < e; k0 += U) {
+    int c[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = k0 + u < e;
+      c[u] = in ? A.ci[k0 + u] : 0;
+      v[u] = in ? A.v[k0 + u] : T(0);
+    }
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = (k0 + u < e) ? (T)x[c[u]] : T(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < e) s += v[u] * xv[u];
+  }
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T csr_row_serial(const DCSR<T>& A, const T* __restrict__ x, int row) {
+  return csr_row_serial_x<T, T>(A, x, row);
 }
 
 template <typename T, int SG, int MODE>
@@ -230,9 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_tcorrect_u(DCSR<T> BT, const T* __re
                                                        T* __restrict__ w_out, int n_u) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n_u) return;
-  T bd = T(0);
-  if (BT.nnz)
-    for (int k = BT.rp[i]; k < BT.rp[i + 1]; ++k) bd += BT.v[k] * delta[BT.ci[k]];
+  const T bd = BT.nnz ? csr_row_serial<T>(BT, delta, i) : T(0);
   const T t = su[i] - alpha * bd;
   const T w = omega * jinv[i] * t;
   znu[i] = (zu ? zu[i] : T(0)) + w;
@@ -336,11 +369,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_u_first_corr(DCSR<T> G, const
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n_u) return;
   T v = omega * jinv[i] * bu[i];
-  if (G.nnz) {
-    T gd = T(0);
-    for (int k = G.rp[i]; k < G.rp[i + 1]; ++k) gd += G.v[k] * delta[G.ci[k]];
-    v -= alpha * ainv[i] * gd;
-  }
+  if (G.nnz) v -= alpha * ainv[i] * csr_row_serial<T>(G, delta, i);
   znu[i] = v;
 }
 
@@ -511,13 +540,6 @@ __device__ __forceinline__ T bell_row(const DBELL<T>& A, const T* __restrict__ x
   return acc;
 }
 
-template <typename T>
-__device__ __forceinline__ T csr_row_serial(const DCSR<T>& A, const T* __restrict__ x, int row) {
-  T s = T(0);
-  for (int k = A.rp[row]; k < A.rp[row + 1]; ++k) s += A.v[k] * x[A.ci[k]];
-  return s;
-}
-
 // Row of a BELL matrix times a vector of another precision (converted on
 // load).
 template <typename T, typename XT, int BS>
@@ -538,13 +560,6 @@ __device__ __forceinline__ T bell_row_x(const DBELL<T>& A, const XT* __restrict_
     }
   }
   return acc;
-}
-
-template <typename T, typename XT>
-__device__ __forceinline__ T csr_row_serial_x(const DCSR<T>& A, const XT* __restrict__ x, int row) {
-  T s = T(0);
-  for (int k = A.rp[row]; k < A.rp[row + 1]; ++k) s += A.v[k] * (T)x[A.ci[k]];
-  return s;
 }
 
 // Block operator apply with x of type XT (x1 = x, x2 = x + n1).  When xcopy
@@ -746,12 +761,17 @@ __global__ void k_hess_solve(const double* __restrict__ H, int ldh, const double
   }
 }
 
+// SG lanes per row, so the column reads and gradient writes of a row are
+// contiguous across the subgroup.
+template <int SG>
 __global__ void __launch_bounds__(kBlock) k_grad_K(DCSR<double> K, const double* __restrict__ lam,
                                                    const double* __restrict__ x, double* __restrict__ dK) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
   if (i >= K.nrows) return;
   const double li = lam[i];
-  for (int k = K.rp[i]; k < K.rp[i + 1]; ++k) dK[k] = -li * x[K.ci[k]];
+  const int e = K.rp[i + 1];
+  for (int k = K.rp[i] + lane; k < e; k += SG) dK[k] = -li * x[K.ci[k]];
 }
 
 template <typename T>
@@ -1189,7 +1209,8 @@ void hess_solve(const double* H, int ldh, const double* g, double* y, int k, hip
 
 void grad_K(const DCSR<double>& K, const double* lam, const double* x, double* dK, hipStream_t s) {
   if (K.nrows <= 0) return;
-  k_grad_K<<<grid_for(K.nrows, kBlock), kBlock, 0, s>>>(K, lam, x, dK);
+  const int sg = pick_subgroup(K.nnz, K.nrows);
+  CAMG_SG_DISPATCH(sg, { k_grad_K<SG><<<grid_for(K.nrows, kBlock / SG), kBlock, 0, s>>>(K, lam, x, dK); });
   CAMG_LAUNCHED();
 }
 
