@@ -16,6 +16,9 @@ namespace camg {
 namespace {
 
 constexpr int kBlock = 256;
+// Levels with more rows than this run the elementwise correction kernels one
+// thread per row; smaller ones give each row a 4-lane subgroup.
+constexpr int kWideRows = 131072;
 
 template <typename T, int SG>
 __device__ __forceinline__ T sg_reduce(T v) {
@@ -257,15 +260,28 @@ __global__ void __launch_bounds__(kBlock) k_tsmooth_l(DCSR<T> GT, DCSR<T> CT, co
   }
 }
 
-template <typename T>
+// Row dot of a short interface row: one thread (SG = 1, chunked loads) or
+// SG lanes reduced across the subgroup (every lane gets the sum).
+template <typename T, int SG>
+__device__ __forceinline__ T short_row_dot(const DCSR<T>& A, const T* __restrict__ x, int row, int lane) {
+  if (SG == 1) return csr_row_serial<T>(A, x, row);
+  return sg_reduce<T, SG>(row_dot<T, SG>(A, x, row, lane));
+}
+
+// SG = 1 on large levels keeps the elementwise streams of one thread per row
+// coalesced; small levels use SG lanes per row so the interface rows' dots do
+// not serialise on one thread.
+template <typename T, int SG>
 __global__ void __launch_bounds__(kBlock) k_tcorrect_u(DCSR<T> BT, const T* __restrict__ su,
                                                        const T* __restrict__ delta, const T* __restrict__ jinv,
                                                        T omega, T alpha, const T* __restrict__ zu,
                                                        T* __restrict__ znu, T* __restrict__ t_out,
                                                        T* __restrict__ w_out, int n_u) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
   if (i >= n_u) return;
-  const T bd = BT.nnz ? csr_row_serial<T>(BT, delta, i) : T(0);
+  const T bd = BT.nnz ? short_row_dot<T, SG>(BT, delta, i, lane) : T(0);
+  if (lane != 0) return;
   const T t = su[i] - alpha * bd;
   const T w = omega * jinv[i] * t;
   znu[i] = (zu ? zu[i] : T(0)) + w;
@@ -360,16 +376,19 @@ __global__ void __launch_bounds__(kBlock) k_schur_jacobi(DCSR<T> S, const T* __r
   }
 }
 
-template <typename T>
+template <typename T, int SG>
 __global__ void __launch_bounds__(kBlock) k_smooth_u_first_corr(DCSR<T> G, const T* __restrict__ bu,
                                                                 const T* __restrict__ jinv, T omega,
                                                                 const T* __restrict__ delta,
                                                                 const T* __restrict__ ainv, T alpha,
                                                                 T* __restrict__ znu, int n_u) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
   if (i >= n_u) return;
+  const T gd = G.nnz ? short_row_dot<T, SG>(G, delta, i, lane) : T(0);
+  if (lane != 0) return;
   T v = omega * jinv[i] * bu[i];
-  if (G.nnz) v -= alpha * ainv[i] * csr_row_serial<T>(G, delta, i);
+  if (G.nnz) v -= alpha * ainv[i] * gd;
   znu[i] = v;
 }
 
@@ -802,10 +821,11 @@ inline unsigned grid_for(int64_t rows, int rows_per_block) {
 // Lanes per row from the mean row length (measured on the contact
 // hierarchies: long coarse rows prefer many lanes for parallel gathers;
 // rows of at most 8 entries, e.g. tentative prolongators, one thread each).
+// Measured on the 40^3 workload's hierarchy: with the unrolled row loop,
+// 16 lanes per row beat 32 and 64 even for rows of 80-160 entries (more
+// rows in flight per wave hide the gather latency better).
 int pick_subgroup(int64_t nnz, int64_t nrows) {
   const double avg = nrows ? (double)nnz / (double)nrows : 0.0;
-  if (avg > 96.0) return 64;
-  if (avg > 40.0) return 32;
   if (avg > 14.0) return 16;
   if (avg > 8.0) return 8;
   return 1;
@@ -959,8 +979,12 @@ template <typename T>
 void tcorrect_u(const DCSR<T>& BT, const T* su, const T* delta, const T* jinv, T omega, T alpha, const T* zu,
                 T* znu, T* t_out, T* w_out, int n_u, bool first, hipStream_t s) {
   if (n_u <= 0) return;
-  k_tcorrect_u<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(BT, su, delta, jinv, omega, alpha, first ? nullptr : zu,
-                                                           znu, t_out, w_out, n_u);
+  if (n_u > kWideRows)
+    k_tcorrect_u<T, 1><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(BT, su, delta, jinv, omega, alpha,
+                                                                first ? nullptr : zu, znu, t_out, w_out, n_u);
+  else
+    k_tcorrect_u<T, 4><<<grid_for(n_u, kBlock / 4), kBlock, 0, s>>>(BT, su, delta, jinv, omega, alpha,
+                                                                    first ? nullptr : zu, znu, t_out, w_out, n_u);
   CAMG_LAUNCHED();
 }
 
@@ -1070,7 +1094,12 @@ template <typename T>
 void smooth_first_u(const DCSR<T>& G, const T* bu, const T* jinv, const T* ainv, const T* delta, T omega, T alpha,
                     T* znu, int n_u, hipStream_t s) {
   if (n_u <= 0) return;
-  k_smooth_u_first_corr<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(G, bu, jinv, omega, delta, ainv, alpha, znu, n_u);
+  if (n_u > kWideRows)
+    k_smooth_u_first_corr<T, 1><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(G, bu, jinv, omega, delta, ainv, alpha, znu,
+                                                                         n_u);
+  else
+    k_smooth_u_first_corr<T, 4><<<grid_for(n_u, kBlock / 4), kBlock, 0, s>>>(G, bu, jinv, omega, delta, ainv, alpha,
+                                                                             znu, n_u);
   CAMG_LAUNCHED();
 }
 

@@ -2,7 +2,7 @@
 //
 // All kernels are deterministic: no atomics, fixed reduction trees, one
 // writer per output element.  Sparse kernels are row-parallel CSR with a
-// subgroup of `sg` lanes per row (4..64) whose column/value streams are
+// subgroup of `sg` lanes per row (1..16) whose column/value streams are
 // read contiguously by the subgroup.
 #pragma once
 
@@ -10,7 +10,7 @@
 
 namespace camg {
 
-// sg: lanes per row, chosen from the dominant block's mean row length.
+// sg: lanes per row (1, 8 or 16), chosen from the mean row length.
 int pick_subgroup(int64_t nnz, int64_t nrows);
 
 // Two-by-two block row SpMV over rows [0, n1) -> (A11 x1 + A12 x2) and rows
