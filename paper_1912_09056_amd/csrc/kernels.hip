@@ -56,6 +56,7 @@ __device__ __forceinline__ void row_dot2(const DCSR<T>& A, const T* __restrict__
   s1 = T(0);
   s2 = T(0);
   const int e = A.rp[row + 1];
+#pragma unroll 4
   for (int k = A.rp[row] + lane; k < e; k += SG) {
     const int c = A.ci[k];
     const T a = A.v[k];
@@ -341,6 +342,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_l_first(DCSR<T> B, const T* _
   T s = T(0);
   if (B.nnz) {
     const int e = B.rp[row + 1];
+#pragma unroll 4
     for (int k = B.rp[row] + lane; k < e; k += SG) {
       const int c = B.ci[k];
       s += B.v[k] * (omega * jinv[c] * bu[c]);
@@ -480,43 +482,56 @@ __global__ void __launch_bounds__(kCgsBlock) k_cgs(const double* __restrict__ V,
 }
 
 // Sum of the nb partials of ||w||^2, then Hessenberg column j = kk - 1 from
-// h1 + h2 and ||w||, its Givens rotation and g (one workgroup).
+// h1 + h2 and ||w||, its Givens rotation and g (one workgroup, kk <= 64).
+// The column and the previous rotations are staged in LDS by all threads, so
+// the serial rotation sweep of thread 0 reads no global memory.
 __global__ void __launch_bounds__(kBlock) k_cgs_finish(const double* __restrict__ partial, int nb, int kk,
                                                        const double* __restrict__ h1, const double* __restrict__ h2,
                                                        double* __restrict__ H, int ldh, double* __restrict__ cs,
                                                        double* __restrict__ sn, double* __restrict__ g,
                                                        double* __restrict__ res) {
   __shared__ double lds[kBlock / 64];
+  __shared__ double col[65], cl[64], sl[64];
+  const int j = kk - 1;
+  for (int i = threadIdx.x; i <= j; i += kBlock) {
+    col[i] = h1[i] + h2[i];
+    if (i < j) {
+      cl[i] = cs[i];
+      sl[i] = sn[i];
+    }
+  }
   double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += kBlock) acc += partial[b];
-  const double hn2 = block_sum(acc, lds);
-  if (threadIdx.x != 0) return;
-  const int j = kk - 1;
-  double* col = H + (int64_t)j * ldh;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  const double hn = sqrt(hn2);
-  col[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = col[i], b = col[i + 1];
-    col[i] = cs[i] * a + sn[i] * b;
-    col[i + 1] = -sn[i] * a + cs[i] * b;
+  const double hn2 = block_sum(acc, lds);  // its barriers also publish the staged column
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(hn2);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = cl[i] * a + sl[i] * b;
+      col[i + 1] = -sl[i] * a + cl[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double d = hypot(a, b);
+    double c = 1.0, sv = 0.0;
+    if (d != 0.0) {
+      c = a / d;
+      sv = b / d;
+    }
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = d;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
+    res[0] = fabs(g[j + 1]);
+    res[1] = hn;
+    res[2] = hn > 0.0 ? 1.0 / hn : 0.0;
   }
-  const double a = col[j], b = col[j + 1];
-  const double d = hypot(a, b);
-  double c = 1.0, sv = 0.0;
-  if (d != 0.0) {
-    c = a / d;
-    sv = b / d;
-  }
-  cs[j] = c;
-  sn[j] = sv;
-  col[j] = d;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sv * g[j];
-  g[j] = c * g[j];
-  res[0] = fabs(g[j + 1]);
-  res[1] = hn;
-  res[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+  __syncthreads();
+  double* hc = H + (int64_t)j * ldh;
+  for (int i = threadIdx.x; i <= j + 1; i += kBlock) hc[i] = col[i];
 }
 
 template <typename T>
@@ -907,16 +922,21 @@ void jacobi_extra(const DCSR<T>& M, const T* w, const T* r, const T* jinv, T ome
   CAMG_LAUNCHED();
 }
 
+// Lanes per row of the multiplier-row kernels: the mean row length rule,
+// at least 4.
+static int rows_sg(int64_t nnz, int64_t rows) { return std::max(4, pick_subgroup(nnz, rows)); }
+
 template <typename T>
 void smooth_l(const DCSR<T>& B, const DCSR<T>& C, const T* znu, const T* zl, const T* bl, const T* sdinv, T alpha,
               T* znl, T* delta, T* rhs_out, int n_l, bool first, hipStream_t s) {
   if (n_l <= 0) return;
-  constexpr int SG = 8;
-  dim3 grid(grid_for(n_l, kBlock / SG));
-  if (first)
-    k_smooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, rhs_out, n_l);
-  else
-    k_smooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, rhs_out, n_l);
+  CAMG_SG_DISPATCH(rows_sg(B.nnz + C.nnz, n_l), {
+    dim3 grid(grid_for(n_l, kBlock / SG));
+    if (first)
+      k_smooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, rhs_out, n_l);
+    else
+      k_smooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(B, C, znu, zl, bl, sdinv, alpha, znl, delta, rhs_out, n_l);
+  });
   CAMG_LAUNCHED();
 }
 
@@ -940,8 +960,9 @@ template <typename T>
 void correct_u(const DCSR<T>& G, const int32_t* rows, int n_rows, const T* delta, const T* ainv, T alpha, T* znu,
                hipStream_t s) {
   if (n_rows <= 0) return;
-  constexpr int SG = 4;
-  k_correct_u<T, SG><<<grid_for(n_rows, kBlock / SG), kBlock, 0, s>>>(G, rows, n_rows, delta, ainv, alpha, znu);
+  CAMG_SG_DISPATCH(rows_sg(G.nnz, n_rows), {
+    k_correct_u<T, SG><<<grid_for(n_rows, kBlock / SG), kBlock, 0, s>>>(G, rows, n_rows, delta, ainv, alpha, znu);
+  });
   CAMG_LAUNCHED();
 }
 
@@ -964,14 +985,15 @@ void tsmooth_l(const DCSR<T>& GT, const DCSR<T>& CT, const T* zu, const T* zl, c
                const T* ainv, const T* sdinv, T alpha, T* znl, T* delta, T* rhs_out, int n_l, bool first,
                hipStream_t s) {
   if (n_l <= 0) return;
-  constexpr int SG = 16;
-  dim3 grid(grid_for(n_l, kBlock / SG));
-  if (first)
-    k_tsmooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta, rhs_out,
-                                                     n_l);
-  else
-    k_tsmooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta,
-                                                      rhs_out, n_l);
+  CAMG_SG_DISPATCH(rows_sg(GT.nnz + CT.nnz, n_l), {
+    dim3 grid(grid_for(n_l, kBlock / SG));
+    if (first)
+      k_tsmooth_l<T, SG, true><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta,
+                                                       rhs_out, n_l);
+    else
+      k_tsmooth_l<T, SG, false><<<grid, kBlock, 0, s>>>(GT, CT, zu, zl, bl, su, ainv, sdinv, alpha, znl, delta,
+                                                        rhs_out, n_l);
+  });
   CAMG_LAUNCHED();
 }
 
@@ -1084,9 +1106,10 @@ template <typename T>
 void smooth_first_l(const DCSR<T>& B, const T* bu, const T* bl, const T* jinv, const T* sdinv, T omega, T alpha,
                     T* znl, T* delta, T* rhs_out, int n_l, hipStream_t s) {
   if (n_l <= 0) return;
-  constexpr int SG = 8;
-  k_smooth_l_first<T, SG><<<grid_for(n_l, kBlock / SG), kBlock, 0, s>>>(B, bu, jinv, omega, bl, sdinv, alpha, znl,
-                                                                        delta, rhs_out, n_l);
+  CAMG_SG_DISPATCH(rows_sg(B.nnz, n_l), {
+    k_smooth_l_first<T, SG><<<grid_for(n_l, kBlock / SG), kBlock, 0, s>>>(B, bu, jinv, omega, bl, sdinv, alpha,
+                                                                          znl, delta, rhs_out, n_l);
+  });
   CAMG_LAUNCHED();
 }
 
