@@ -66,6 +66,59 @@ def smooth_u_bytes(info0, elem):
     return info0["nnz_K"] * (elem + 4) + (n_u + 1) * 4 + vec
 
 
+def vcycle_matrix_bytes(solver, elem):
+    """Matrix bytes streamed by one forward V-cycle (a lower bound on its
+    traffic: vectors excluded).  Per smoothing level with nu_pre + nu_post
+    sweeps of nj Jacobi steps: K is read (nu_pre + nu_post) * nj times (each
+    sweep but the first from zero, its extra Jacobi steps, and the residual
+    before restriction); G twice per sweep plus the residual; B and C once
+    per sweep plus the residual; R and P once.  K in its device layout
+    (3x3 blocks with a 4-byte index, or CSR), the other blocks CSR
+    (value + 4-byte column).  The coarsest level: its dense inverse."""
+    o = solver.options
+    sweeps = o.nu_pre + o.nu_post
+    nj = max(1, o.jacobi_sweeps)
+    total = 0
+    for l in range(solver.n_levels):
+        info = solver.level_info(l)
+        if l == solver.n_levels - 1:
+            n = info["n_u"] + info["n_l"]
+            total += n * n * elem
+            break
+        if info["k_layout"] == 1:
+            kb = info["k_blocks"] * (info["k_bs"] ** 2 * elem + 4)
+        else:
+            kb = info["nnz_K"] * (elem + 4)
+        e = elem + 4
+        total += sweeps * nj * kb
+        total += (2 * sweeps + 1) * info["nnz_G"] * e
+        total += (sweeps + 1) * (info["nnz_B"] + info["nnz_C"]) * e
+        total += 2 * (solver.level_matrix(l, "P_u").nnz + solver.level_matrix(l, "P_l").nnz) * e
+    return total
+
+
+def time_vcycles(solver, reps=50):
+    """Seconds per forward V-cycle application (graph replay, hipEvents)."""
+    import torch
+
+    r = torch.from_numpy(np.random.default_rng(0).standard_normal(solver.n)).cuda()
+    for _ in range(3):
+        solver.vcycle(r)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        solver.vcycle(r)
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) * 1e-3 / reps
+
+
+PAPER_CONTEXT = ("The paper reports no GPU, per-solve or bandwidth figures for this path: its CheapSIMPLE "
+                 "PA-AMG runs used GMRES to 1e-8 on 2x Xeon E5-2670 (16 cores), e.g. 20.5 GMRES iterations per "
+                 "Newton step on a 6,300-unknown two-body problem (3 levels), and whole-simulation linear-solver "
+                 "totals of 21,883 s (2D rings) and 16,288 s (3D tori) including a hierarchy rebuild every Newton "
+                 "step.")
+
 PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_smooth_u_bell_contact3d_40.md")
 KERNELS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1912_09056_amd", "csrc", "kernels.hip")
 
@@ -109,12 +162,13 @@ def main():
     top = torch.from_numpy(prob.top_dofs).cuda()
     b = torch.from_numpy(prob.b).cuda()
 
-    solvers = {}
+    solvers, setup_s = {}, {}
     for name, prec in (("mixed", 1), ("fp64", 0)):
         t1 = time.time()
         solvers[name] = AMGSolver.from_problem(
             prob, AMGOptions(max_levels=args.levels, precision=prec, spmv_format=args.spmv_format))
-        print(f"[bench] setup {name}: {time.time() - t1:.1f}s levels={solvers[name].n_levels}", file=sys.stderr,
+        setup_s[name] = time.time() - t1
+        print(f"[bench] setup {name}: {setup_s[name]:.1f}s levels={solvers[name].n_levels}", file=sys.stderr,
               flush=True)
 
     def step(s):
@@ -125,7 +179,7 @@ def main():
         dK = s.grad_K(lam, x)
         return fi, ai, dK
 
-    results = {}
+    results, xs = {}, {}
     for name in ("fp64", "mixed"):
         s = solvers[name]
         for _ in range(args.warmup):
@@ -140,6 +194,8 @@ def main():
         torch.cuda.synchronize()
         t_end = time.perf_counter()
         results[name] = dict(fwd=fwd, adj=adj, wall=(t_end - t_start) / args.steps)
+        xs[name] = s.solve(b, rtol=1e-8)[0].cpu().numpy()
+        results[name]["vcycle_s"] = time_vcycles(s)
         if name == "mixed":
             # per-launch durations of the level-0 smoother kernel: hipEvents
             # around every launch on the solver's stream during one more step
@@ -168,6 +224,9 @@ def main():
     bytes_per = smooth_u_bytes(info0, 4)
     achieved = bytes_per / avg_s / 1e9
     peak = 8000.0
+    traffic = measured_traffic() if info0["k_layout"] == 1 else None
+    vc_bytes = {"mixed": vcycle_matrix_bytes(solvers["mixed"], 4), "fp64": vcycle_matrix_bytes(solvers["fp64"], 8)}
+    diff = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
 
     out = {
         "metric": "solve time to rel. residual 1e-8 (s), V-cycle GB/s vs HBM peak: mixed vs FP64",
@@ -195,6 +254,9 @@ def main():
             "iters": int(np.median([f["iters"] for f in mixed["fwd"]])),
             "adjoint_s": float(np.median([a["seconds"] for a in mixed["adj"]])),
             "adjoint_iters": int(np.median([a["iters"] for a in mixed["adj"]])),
+            "setup_s": setup_s["mixed"],
+            "vcycles_per_s": 1.0 / mixed["vcycle_s"],
+            "vcycle_matrix_GBps": vc_bytes["mixed"] / mixed["vcycle_s"] / 1e9,
         },
         "fp64": {
             "solve_s": solve_fp64,
@@ -202,8 +264,15 @@ def main():
             "adjoint_s": float(np.median([a["seconds"] for a in fp64["adj"]])),
             "adjoint_iters": int(np.median([a["iters"] for a in fp64["adj"]])),
             "ms_per_step": fp64["wall"] * 1e3,
+            "setup_s": setup_s["fp64"],
+            "vcycles_per_s": 1.0 / fp64["vcycle_s"],
+            "vcycle_matrix_GBps": vc_bytes["fp64"] / fp64["vcycle_s"] / 1e9,
         },
+        "vcycle_bytes_model": "matrix streams of one forward V-cycle (K in its device layout, G, B, C, R, P, the "
+                              "dense coarsest inverse), vectors excluded: a lower bound on its traffic",
         "speedup_mixed_vs_fp64": solve_fp64 / solve_mixed,
+        "mixed_vs_fp64_solution_rel_diff": diff,
+        "paper_context": PAPER_CONTEXT,
         "roofline": {
             "kernel": "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell: sliced blocked-ELL K)"
                       if info0["k_layout"] == 1 else "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u: CSR K)",
@@ -212,7 +281,8 @@ def main():
             "peak": peak,
             "unit": "GB/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic() if info0["k_layout"] == 1 else None,
+            "traffic": traffic,
+            "achieved_from_counters_GBps": traffic / avg_s / 1e9 if traffic else None,
             "bytes_per_launch": bytes_per,
             "bytes_model": "nonzero 3x3 blocks of K (9 FP32 values + 4-byte block index each) + G CSR + "
                            "5 FP32 vectors of n_u, read or written once",
@@ -225,14 +295,22 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args, out["fp64"]["iters"])
+        out["cpu_baseline"], x_ref = cpu_baseline(prob, args, out["fp64"]["iters"])
+        ref = np.linalg.norm(x_ref)
+        out["error_vs_oracle"] = {
+            "reference": "FP64 oracle solve to relative residual 1e-12 on the host",
+            "mixed": float(np.linalg.norm(xs["mixed"] - x_ref) / ref),
+            "fp64": float(np.linalg.norm(xs["fp64"] - x_ref) / ref),
+        }
     print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(prob, args, iters_to_tol):
     """The FP64 oracle on the host: a bounded sample of FGMRES iterations
     (fixed count, setup excluded), scaled to the iteration count that
-    reaches 1e-8 (the GPU FP64 path's count, which matches the oracle's)."""
+    reaches 1e-8 (the GPU FP64 path's count, which matches the oracle's).
+    Also returns the oracle's solution at relative residual 1e-12 (untimed),
+    the reference for the GPU solutions' error."""
     from threadpoolctl import threadpool_info
 
     from oracle.adjoint import solve as oracle_solve
@@ -249,6 +327,10 @@ def cpu_baseline(prob, args, iters_to_tol):
     t = time.perf_counter() - t0
     threads = max([1] + [p.get("num_threads", 1) for p in threadpool_info()])
     print(f"[bench] cpu oracle: setup {t_setup:.1f}s, {k} iterations {t:.1f}s", file=sys.stderr, flush=True)
+    # reference solution for the error figures (not timed)
+    t0 = time.time()
+    x_ref = oracle_solve(lv, opts, prob.b, rtol=1e-12, max_iters=400).x
+    print(f"[bench] oracle reference solve {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     return {
         "value": t / k * iters_to_tol,
         "unit": "s",
@@ -257,7 +339,7 @@ def cpu_baseline(prob, args, iters_to_tol):
         "sample": f"{k} FGMRES(50) iterations of the FP64 numpy/scipy oracle on the same problem "
                   f"(setup excluded), scaled to {iters_to_tol} iterations",
         "setup_s": t_setup,
-    }
+    }, x_ref
 
 
 if __name__ == "__main__":
