@@ -99,6 +99,8 @@ typedef struct {
 #define CAMG_PROLONG_SMOOTHED 1  /* ... smoothed aggregation (SA)           */
 #define CAMG_SCHUR_DIAG 0        /* Schur diagonal: diag(B Atilde^-1 G - C) */
 #define CAMG_SCHUR_L1 1          /* ... signed l1 row sums of that matrix   */
+#define CAMG_COARSE_LU 0         /* coarsest level: merged dense LU inverse */
+#define CAMG_COARSE_SIMPLE 1     /* ... CheapSIMPLE sweeps from zero        */
 typedef struct {
   int32_t max_levels;      /* >= 1; 1 = direct solve of the whole system  */
   int32_t max_coarse_rows; /* stop coarsening at or below this many rows   */
@@ -125,6 +127,13 @@ typedef struct {
   int32_t schur;           /* CAMG_SCHUR_*                                 */
   int32_t schur_sweeps;    /* 1..64                                        */
   double sa_omega;         /* prolongator smoothing factor, > 0            */
+  /* Coarsest-level solver (the two variants of the weak-scaling study,
+   * Sec. 6.2): CAMG_COARSE_LU merges the blocks and applies the explicit
+   * inverse; CAMG_COARSE_SIMPLE runs coarse_sweeps CheapSIMPLE sweeps from
+   * zero there (adjoint sweeps in the transposed cycle), with no merge and no
+   * factorisation, so a singular coarsest matrix is no error. */
+  int32_t coarse_solver;   /* CAMG_COARSE_*                                */
+  int32_t coarse_sweeps;   /* 1..64                                        */
 } amg_options;
 
 /* FGMRES options. */

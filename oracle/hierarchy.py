@@ -18,7 +18,10 @@ Paper passages followed:
 * optionally, smoothed aggregation for the displacement transfers
   (Sec. 3.1.2, prolongator smoothing equation; the weak-scaling settings
   smooth the displacement prolongator with omega = 4/3 and keep the
-  multiplier transfers unsmoothed).
+  multiplier transfers unsmoothed);
+* optionally, the CheapSIMPLE level smoother instead of the direct solve on
+  the coarsest level (the second coarse-solver variant of the weak-scaling
+  study), which needs smoother data there and no merged factorisation.
 
 Readings where the paper is silent (all listed in the design notes):
 * Dirichlet dof = row of K whose only stored entry is its diagonal and whose
@@ -66,6 +69,8 @@ class AMGOptions:
     sa_omega: float = 4.0 / 3.0  # prolongator smoothing factor (with the lumped diagonal)
     schur: str = "diag"  # diagonal of the Schur approximation: "diag" or "l1"
     schur_sweeps: int = 1  # Jacobi sweeps on the Schur system (1 = divide by the diagonal)
+    coarse_solver: str = "lu"  # coarsest level: "lu" (merged dense LU) or "simple" (CheapSIMPLE sweeps)
+    coarse_sweeps: int = 2  # sweeps from zero on the coarsest level with "simple"
 
 
 @dataclass
@@ -472,9 +477,10 @@ def build_hierarchy(prob, opts: AMGOptions = None, factor_coarsest: bool = True)
         if nxt.n >= levels[-1].n:
             break
         levels.append(nxt)
-    for L in levels[:-1]:
+    simple_coarse = opts.coarse_solver == "simple"
+    for L in levels if simple_coarse else levels[:-1]:
         smoother_data(L, opts)
-    if factor_coarsest:
+    if factor_coarsest and not simple_coarse:
         coarse_inverse(levels[-1])
     return levels
 

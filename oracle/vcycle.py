@@ -11,6 +11,11 @@ The transposed cycle applies exactly M^-T for the forward cycle's M^-1: the
 same recursion on A^T with the adjoint sweep, the pre/post sweep counts
 swapped, restriction P^T and prolongation R^T (identical to the forward
 transfers because R = P^T), and A_c^-T on the coarsest level.
+
+With the CheapSIMPLE coarse solver (the weak-scaling study's second
+variant) the coarsest level runs `coarse_sweeps` sweeps from zero instead of
+the direct solve.  k sweeps from zero give I - M_k A = (I - Q^-1 A)^k, whose
+transpose is k adjoint sweeps from zero, so the transposed cycle stays exact.
 """
 from __future__ import annotations
 
@@ -30,7 +35,8 @@ def _apply_A(L, z, transpose):
 def vcycle(levels, b, opts, level=0, transpose=False):
     """z = M^-1 b (or M^-T b) for the hierarchy starting at `level`."""
     L = levels[level]
-    if level == len(levels) - 1:
+    coarsest = level == len(levels) - 1
+    if coarsest and opts.coarse_solver != "simple":
         return (L.A_inv.T if transpose else L.A_inv) @ b
     if transpose:
         n_pre, n_post = opts.nu_post, opts.nu_pre
@@ -48,6 +54,10 @@ def vcycle(levels, b, opts, level=0, transpose=False):
 
     n_u = L.n_u
     z = np.zeros_like(b)
+    if coarsest:
+        for _ in range(opts.coarse_sweeps):
+            z = sweep(b, z)
+        return z
     for _ in range(n_pre):
         z = sweep(b, z)
     r = b - _apply_A(L, z, transpose)

@@ -75,6 +75,8 @@ class amg_options(Structure):
         ("schur", c_int32),
         ("schur_sweeps", c_int32),
         ("sa_omega", c_double),
+        ("coarse_solver", c_int32),
+        ("coarse_sweeps", c_int32),
     ]
 
 
@@ -203,6 +205,8 @@ class AMGOptions:
     schur: int = 0  # Schur diagonal: 0 diag(S), 1 signed l1 row sums
     schur_sweeps: int = 1  # Jacobi sweeps on the Schur system (1 = division by the diagonal)
     sa_omega: float = 4.0 / 3.0
+    coarse_solver: int = 0  # coarsest level: 0 dense LU inverse, 1 CheapSIMPLE sweeps
+    coarse_sweeps: int = 2
 
     def to_c(self) -> amg_options:
         o = amg_options()

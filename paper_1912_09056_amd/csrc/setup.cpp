@@ -29,6 +29,9 @@
 //    Atilde = diag(sum_j |K_ij|), whose bound lambda(Atilde^-1 K) <= 1 lets
 //    the printed omega = 4/3 be used as is; pattern = P_tent's plus the
 //    symbolic pattern of K P_tent.
+//  * Optional CheapSIMPLE coarse solver (the weak-scaling study's second
+//    coarse-solver variant): smoother data on the coarsest level too, no
+//    merged matrix and no factorisation.
 //  * Optional Schur sweeps: S = B Atilde^-1 G - C on the symbolic pattern of
 //    B G plus C's, diagonal either S_jj or sign(S_jj) sum_k |S_jk|.
 #include "setup.hpp"
@@ -683,8 +686,9 @@ void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt) {
     }
     levels.push_back(std::move(nxt));
   }
-  for (size_t l = 0; l + 1 < levels.size(); ++l) smoother_data(levels[l], opt);
-  coarse_inverse(levels.back());
+  const size_t n_smooth = opt.simple_coarse ? levels.size() : levels.size() - 1;
+  for (size_t l = 0; l < n_smooth; ++l) smoother_data(levels[l], opt);
+  if (!opt.simple_coarse) coarse_inverse(levels.back());
 }
 
 }  // namespace camg

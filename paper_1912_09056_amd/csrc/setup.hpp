@@ -42,7 +42,7 @@ struct HostLevel {
   HostCSR P_u, P_l;
   std::vector<double> atilde_inv, jac_inv, sd_inv;
   HostCSR S;                       // B Atilde^-1 G - C (only when relaxed by Jacobi sweeps)
-  std::vector<double> Ainv;        // coarsest level: dense inverse, row-major
+  std::vector<double> Ainv;        // coarsest level with the direct solve: dense inverse, row-major
   int64_t n_u() const { return K.nrows; }
   int64_t n_l() const { return C.nrows; }
   int64_t n() const { return n_u() + n_l(); }
@@ -58,6 +58,7 @@ struct SetupOptions {
   double sa_omega = 4.0 / 3.0;
   int schur = 0;         // 0 diagonal of S, 1 signed l1 row sums of S
   int schur_sweeps = 1;  // > 1: keep S for Jacobi sweeps
+  bool simple_coarse = false;  // coarsest level smooths (smoother data, no dense inverse)
 };
 
 // Status codes mirror the C-ABI's CAMG_* values.

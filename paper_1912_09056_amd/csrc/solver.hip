@@ -327,8 +327,10 @@ static HostCSR to_host(const amg_csr& A) {
   return H;
 }
 
+// dense_coarse: the level is the coarsest one and is solved with its dense
+// inverse (otherwise it smooths and needs the smoother diagonals).
 template <typename T>
-static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool coarsest, hipStream_t s) {
+static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool dense_coarse, hipStream_t s) {
   const int64_t n = H.n(), nu = H.n_u(), nl = H.n_l();
   for (DBuf<T>* b : {&V.b, &V.z, &V.zn, &V.r}) {
     b->alloc((size_t)n);
@@ -347,7 +349,7 @@ static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool coarsest, hipSt
     d.upload(t, s);
     CAMG_HIP(hipStreamSynchronize(s));
   };
-  if (!coarsest) {
+  if (!dense_coarse) {
     up(V.jinv, H.jac_inv);
     up(V.ainv, H.atilde_inv);
     up(V.sdinv, H.sd_inv);
@@ -415,6 +417,10 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       upload_mat(D.Rl, Rl, t64, f32, s);
       D.sg_R = pick_subgroup(Ru.nnz(), Ru.nrows);
       D.sg_P = pick_subgroup(H.P_u.nnz(), H.P_u.nrows);
+    }
+    const bool dense_coarse = coarsest && h.opts.coarse_solver == CAMG_COARSE_LU;
+    if (!dense_coarse) {
+      const bool t64 = !mixed;
       if (H.S.nrows > 0) {
         upload_mat(D.S, H.S, t64, f32, s);
         upload_mat(D.ST, transpose(H.S), t64, f32, s);
@@ -426,8 +432,8 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       D.n_g_rows = (int32_t)gr.size();
       D.g_rows.upload(gr, s);
     }
-    if (mixed) alloc_vecs<float>(D.v32, H, coarsest, s);
-    else alloc_vecs<double>(D.v64, H, coarsest, s);
+    if (mixed) alloc_vecs<float>(D.v32, H, dense_coarse, s);
+    else alloc_vecs<double>(D.v64, H, dense_coarse, s);
     if (mixed && l == 0) {
       // FP64 level-0 vectors for operator applies outside the V-cycle
       D.v64.r.alloc((size_t)H.n());
@@ -539,9 +545,20 @@ static T* vcycle_level(amg_handle& h, int l, bool transpose, hipStream_t s) {
   LevelVecs<T>& V = vecs<T>(D);
   const int nu = (int)D.n_u, nl = (int)D.n_l;
   const int last = (int)h.lev.size() - 1;
-  if (l == last) {
+  if (l == last && h.opts.coarse_solver == CAMG_COARSE_LU) {
     dense_gemv<T>(transpose ? V.AinvT.p : V.Ainv.p, V.b.p, V.z.p, (int)D.n(), s);
     return V.z.p;
+  }
+  if (l == last) {
+    // CheapSIMPLE coarse solver: coarse_sweeps sweeps from zero (adjoint
+    // sweeps for the transposed cycle)
+    T* zc = V.z.p;
+    T* zx = V.zn.p;
+    for (int k = 0; k < h.opts.coarse_sweeps; ++k) {
+      sweep<T>(h, l, transpose, V.b.p, zc, zx, k == 0, s);
+      std::swap(zc, zx);
+    }
+    return zc;
   }
   const int npre = transpose ? h.opts.nu_post : h.opts.nu_pre;
   const int npost = transpose ? h.opts.nu_pre : h.opts.nu_post;
@@ -892,6 +909,8 @@ void amg_default_options(amg_options* o) {
   o->schur = CAMG_SCHUR_DIAG;
   o->schur_sweeps = 1;
   o->sa_omega = 4.0 / 3.0;
+  o->coarse_solver = CAMG_COARSE_LU;
+  o->coarse_sweeps = 2;
 }
 
 void amg_default_gmres_options(amg_gmres_options* o) {
@@ -917,7 +936,8 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
       (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 1 ||
       o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
       o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 1 || o.schur_sweeps < 1 ||
-      o.schur_sweeps > 64 || !(o.sa_omega > 0.0) || !std::isfinite(o.sa_omega))
+      o.schur_sweeps > 64 || !(o.sa_omega > 0.0) || !std::isfinite(o.sa_omega) || o.coarse_solver < 0 ||
+      o.coarse_solver > 1 || o.coarse_sweeps < 1 || o.coarse_sweeps > 64)
     api_fail(CAMG_ERR_INVALID_ARG, "invalid options");
   const int64_t nu = p->K.nrows, nl = p->C.nrows;
   if (nu <= 0 || nu % p->dim) api_fail(CAMG_ERR_SHAPE, "n_u must be a positive multiple of dim");
@@ -987,6 +1007,7 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   so.sa_omega = o.sa_omega;
   so.schur = o.schur;
   so.schur_sweeps = o.schur_sweeps;
+  so.simple_coarse = o.coarse_solver == CAMG_COARSE_SIMPLE;
   build_hierarchy(h->host, so);
   return h;
 }

@@ -320,6 +320,49 @@ def test_robust_options_three_level(fmt):
         assert _rel(x.cpu().numpy(), ref.x) < 1e-10, tr
 
 
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_simple_coarse_solver(fmt):
+    """CheapSIMPLE sweeps instead of the LU on the coarsest level: V-cycle and
+    its transpose (FP64; mixed to FP32 accuracy) and fixed-iteration FGMRES
+    against the oracle on a three-level 2D hierarchy, default and robust
+    smoother settings."""
+    prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=14)
+    for okw, lkw in (({}, {}), (ROBUST_ORACLE, ROBUST_LIB)):
+        kw = dict(max_levels=3, max_coarse_rows=50, coarse_sweeps=3)
+        oopts = OracleOptions(**kw, coarse_solver="simple", **okw)
+        lv = build_hierarchy(prob, oopts)
+        r = np.random.default_rng(15).standard_normal(prob.n)
+        for prec, tol in ((0, 1e-12), (1, 2e-5)):
+            s = _solver(prob, precision=prec, fmt=fmt, coarse_solver=1, **kw, **lkw)
+            for tr in (False, True):
+                z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+                assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < tol, (okw, prec, tr)
+        s = _solver(prob, fmt=fmt, coarse_solver=1, **kw, **lkw)
+        ref = oracle_solve(lv, oopts, prob.b, m=10, fixed_iters=25)
+        x, info = s.solve(torch.from_numpy(prob.b), m=10, fixed_iters=25)
+        assert _rel(x.cpu().numpy(), ref.x) < 1e-10, okw
+
+
+def test_simple_coarse_solver_converges():
+    """3D 6^3 workload, two levels, CheapSIMPLE on the coarsest level: both
+    precisions reach 1e-8 (true residual) and the FP64 iteration count
+    matches the oracle's."""
+    prob = make_workload("contact3d_6")
+    A = prob.full_matrix()
+    oopts = OracleOptions(max_levels=2, coarse_solver="simple", coarse_sweeps=3)
+    ref = oracle_solve(build_hierarchy(prob, oopts), oopts, prob.b, rtol=1e-8, max_iters=500)
+    assert ref.converged
+    for prec in (0, 1):
+        s = _solver(prob, precision=prec, max_levels=2, coarse_solver=1, coarse_sweeps=3)
+        x, info = s.solve(torch.from_numpy(prob.b), rtol=1e-8, max_iters=500)
+        print(f"[simple-coarse] prec={prec} iters={info['iters']} oracle={ref.iters}", flush=True)
+        assert info["converged"], (prec, info)
+        x = x.cpu().numpy()
+        assert np.linalg.norm(prob.b - A @ x) <= 1.0001e-8 * np.linalg.norm(prob.b)
+        if prec == 0:
+            assert abs(info["iters"] - ref.iters) <= 1
+
+
 def test_bench_workload_parity():
     """The 40^3 / 41x41x40 workload at full size, in the launch configuration the
     benchmark times: V-cycle (FP64) against the oracle on a seeded vector, and both

@@ -176,3 +176,21 @@ def test_robust_options_validated():
         with pytest.raises(CamgError) as e:
             AMGSolver.from_problem(p, AMGOptions(max_levels=2, **bad), host_only=True)
         assert e.value.code == -1, bad
+
+
+def test_simple_coarse_solver_host_setup():
+    # the 3-level 6^3 hierarchy is singular on its coarsest level: the LU
+    # variant reports SINGULAR_COARSE, the CheapSIMPLE variant builds
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver, CamgError
+
+    p = make_workload("contact3d_6")
+    with pytest.raises(CamgError) as e:
+        AMGSolver.from_problem(p, AMGOptions(max_levels=3, max_coarse_rows=10), host_only=True)
+    assert e.value.code == -6
+    s = AMGSolver.from_problem(p, AMGOptions(max_levels=3, max_coarse_rows=10, coarse_solver=1, coarse_sweeps=3),
+                               host_only=True)
+    assert s.n_levels == 3
+    for bad in (dict(coarse_solver=2), dict(coarse_solver=1, coarse_sweeps=0), dict(coarse_sweeps=65)):
+        with pytest.raises(CamgError) as e:
+            AMGSolver.from_problem(p, AMGOptions(max_levels=2, **bad), host_only=True)
+        assert e.value.code == -1, bad

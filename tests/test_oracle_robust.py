@@ -146,3 +146,54 @@ def test_robust_settings_converge_under_contrast():
     r0 = solve(build_hierarchy(p, base), base, p.b, rtol=1e-8, max_iters=400)
     assert r.converged and r.rel_res_true <= 1e-8
     assert r.iters < r0.iters
+
+
+def _simple_coarse(**kw):
+    return AMGOptions(max_levels=2, coarse_solver="simple", **kw)
+
+
+def test_simple_coarse_solver_is_k_stationary_steps():
+    # k smoother sweeps from zero as the coarse "solve": with the one-sweep
+    # matrix Q^-1 (a sweep from zero) the k-step operator has the closed form
+    # M_k = (I - (I - Q^-1 A)^k) A^-1.  One-level hierarchy of the 2D workload
+    # (the coarsest level is the whole system), dense check.
+    p = make_workload("contact2d_16")
+    o = AMGOptions(max_levels=1, coarse_solver="simple", coarse_sweeps=3)
+    lv = build_hierarchy(p, o)
+    assert len(lv) == 1 and lv[0].A_inv is None
+    L = lv[0]
+    A = L.A().toarray()
+    n = A.shape[0]
+    I = np.eye(n)
+    Qinv = np.column_stack([cheap_simple_sweep(L, e, np.zeros(n), o.jacobi_omega, o.simple_alpha) for e in I])
+    Mk = (I - np.linalg.matrix_power(I - Qinv @ A, 3)) @ np.linalg.inv(A)
+    r = np.random.default_rng(2).standard_normal(n)
+    z = vcycle(lv, r, o)
+    assert np.linalg.norm(z - Mk @ r) <= 1e-10 * np.linalg.norm(z)
+    zt = vcycle(lv, r, o, transpose=True)
+    assert np.linalg.norm(zt - Mk.T @ r) <= 1e-10 * np.linalg.norm(zt)
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_simple_coarse_solver_transpose_dot_product(sweeps):
+    p = make_workload("contact3d_6")
+    o = AMGOptions(max_levels=2, coarse_solver="simple", coarse_sweeps=sweeps, schur="l1", schur_sweeps=2)
+    lv = build_hierarchy(p, o)
+    rng = np.random.default_rng(13)
+    x, y = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    a1 = y @ vcycle(lv, x, o)
+    a2 = vcycle(lv, y, o, transpose=True) @ x
+    assert abs(a1 - a2) <= 1e-12 * abs(a1)
+
+
+def test_simple_coarse_solver_needs_no_factorisation():
+    # the 3-level 6^3 hierarchy's merged coarsest matrix is singular, so the
+    # LU variant cannot be built; the smoother variant builds (no merge, no
+    # factorisation)
+    from oracle.hierarchy import SingularCoarse
+
+    p = make_workload("contact3d_6")
+    with pytest.raises(SingularCoarse):
+        build_hierarchy(p, AMGOptions(max_levels=3, max_coarse_rows=10))
+    lv = build_hierarchy(p, AMGOptions(max_levels=3, max_coarse_rows=10, coarse_solver="simple"))
+    assert len(lv) == 3 and lv[-1].A_inv is None and lv[-1].sd_inv is not None
