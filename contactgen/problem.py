@@ -15,8 +15,10 @@ The synthetic instance is linear elasticity of two structured blocks glued by
 frictionless contact in which every slave node is active:
 
 * slave body on top, master body below, flat (or smoothly curved) interface;
-* dual mortar basis, so D is diagonal (Sec. 2.2); multipliers are Cartesian,
-  d per slave interface node (Sec. 2.3 remark on the Cartesian frame);
+* dual mortar basis, so D is diagonal (Sec. 2.2), or optionally the standard
+  basis of the weak-scaling study (D the interface mass matrix); multipliers
+  are Cartesian, d per slave interface node (Sec. 2.3 remark on the
+  Cartesian frame);
 * G = [D; -M^T] (x) I_d on slave / master interface rows;
 * constraint row of slave node j: the normal slot holds n_j^T (x) [D_j, -M_j]
   (weighted-gap linearisation); the tangential slots hold tau_a^T acting on
@@ -190,6 +192,9 @@ def make_contact_problem(
     top_bc: str = "roller",
     seed: int = 0,
     rhs: str = "load",
+    lm_basis: str = "dual",
+    E: float = 1.0,
+    penetration: float = 0.0,
 ) -> ContactProblem:
     """Build a two-block contact problem (see module docstring).
 
@@ -204,7 +209,14 @@ def make_contact_problem(
     top_bc: slave top face condition: "roller" fixes the tangential
         components, "clamped" all components (then K alone is nonsingular),
         "free" none (the slave body can slide and the operator is singular).
-    rhs: "load" (consistent traction forces) or "random" (seeded U(-1,1)).
+    rhs: "load" (consistent traction forces), "random" (seeded U(-1,1)) or
+        "gap": no load; the blocks overlap by `penetration` along the
+        interface normal, so each normal constraint row asks
+        n_j . (D u_s - M u_m)_j = penetration * sum_k D_jk (the weighted gap
+        g~_j = int N_j g0 with g0 = -penetration, moved to the right-hand
+        side: the slave moves away from the master by the overlap).
+    lm_basis: "dual" (diagonal D) or "standard" (D = interface mass matrix).
+    E: Young's modulus scale (times the lognormal factor when E_sigma > 0).
     """
     slave_elems = list(slave_elems)
     master_elems = list(master_elems)
@@ -217,14 +229,14 @@ def make_contact_problem(
     n_el_s = int(np.prod(slave_elems))
     n_el_m = int(np.prod(master_elems))
     if E_sigma > 0.0:
-        E = rng.lognormal(0.0, E_sigma, n_el_s + n_el_m)
+        Ee = E * rng.lognormal(0.0, E_sigma, n_el_s + n_el_m)
     else:
-        E = np.ones(n_el_s + n_el_m)
+        Ee = np.full(n_el_s + n_el_m, float(E))
     if isinstance(nu, (tuple, list)):
         nus = rng.uniform(nu[0], nu[1], n_el_s + n_el_m)
     else:
         nus = np.full(n_el_s + n_el_m, float(nu))
-    lam, mu = lame_from_E_nu(E, nus)
+    lam, mu = lame_from_E_nu(Ee, nus)
 
     axes_s = _grid_coords(slave_elems, *slave_box)
     axes_m = _grid_coords(master_elems, *master_box)
@@ -298,10 +310,14 @@ def make_contact_problem(
     weights = None
     if fprime is not None:
         weights = [lambda x: np.sqrt(1.0 + fprime(x) ** 2), None]
-    Dd, Mf = mortar_face(face_s, face_m, weights)
+    Dm, Mf = mortar_face(face_s, face_m, weights, lm_basis)
     ns = len(slave_iface_nodes)
     nm = len(master_iface_nodes)
-    assert Dd.shape == (ns,) and Mf.shape == (ns, nm)
+    Dsp = sp.diags(Dm).tocsr() if Dm.ndim == 1 else sp.csr_matrix(Dm)
+    Dsp.eliminate_zeros()
+    Dcoo = Dsp.tocoo()
+    D_rowsum = np.asarray(Dsp.sum(axis=1)).ravel()
+    assert Dsp.shape == (ns, ns) and Mf.shape == (ns, nm)
     n_lam = dim * ns
 
     # normals / tangents per slave interface node (the +x_dim-facing normal)
@@ -327,9 +343,9 @@ def make_contact_problem(
     # G = [D; -M^T] (x) I_d
     g_rows, g_cols, g_vals = [], [], []
     for c in range(dim):
-        g_rows.append(slave_iface_nodes * dim + c)
-        g_cols.append(np.arange(ns) * dim + c)
-        g_vals.append(Dd)
+        g_rows.append(slave_iface_nodes[Dcoo.col] * dim + c)
+        g_cols.append(Dcoo.row * dim + c)
+        g_vals.append(Dcoo.data)
         g_rows.append(master_iface_nodes[Mcoo.col] * dim + c)
         g_cols.append(Mcoo.row * dim + c)
         g_vals.append(-Mcoo.data)
@@ -341,9 +357,9 @@ def make_contact_problem(
     b_rows, b_cols, b_vals = [], [], []
     for c in range(dim):
         nc = normals[:, c]
-        b_rows.append(np.arange(ns) * dim + last)
-        b_cols.append(slave_iface_nodes * dim + c)
-        b_vals.append(nc * Dd)
+        b_rows.append(Dcoo.row * dim + last)
+        b_cols.append(slave_iface_nodes[Dcoo.col] * dim + c)
+        b_vals.append(nc[Dcoo.row] * Dcoo.data)
         b_rows.append(Mcoo.row * dim + last)
         b_cols.append(master_iface_nodes[Mcoo.col] * dim + c)
         b_vals.append(-nc[Mcoo.row] * Mcoo.data)
@@ -383,6 +399,9 @@ def make_contact_problem(
         b = np.zeros(n_u + n_lam)
         face_top = [axes_s[a] for a in range(dim - 1)]
         b[top_dofs] = traction * _face_weights(face_top)
+    elif rhs == "gap":
+        b = np.zeros(n_u + n_lam)
+        b[n_u + np.arange(ns) * dim + last] = penetration * D_rowsum
     elif rhs == "random":
         b = rng.uniform(-1.0, 1.0, n_u + n_lam)
     else:
@@ -478,10 +497,13 @@ def make_workload(name: str, seed: int = 0, rhs: str = "load", **overrides) -> C
     return make_contact_problem(seed=seed, rhs=rhs, **params)
 
 
-def weak_scaling_problem(kappa: int, seed: int = 0) -> ContactProblem:
-    """Geometry of the paper's weak-scaling study (its setup subsection): a
-    0.8 x 0.8 x 0.4 slave block on a 1.0 x 1.0 x 0.5 master block, each with
-    2*kappa elements along its long edges and kappa along the short one."""
+def weak_scaling_problem(kappa: int, seed: int = 0, lm_basis: str = "standard", rhs: str = "gap") -> ContactProblem:
+    """The paper's weak-scaling problem (Sec. 6.2 setup): a 0.8 x 0.8 x 0.4
+    slave block on a 1.0 x 1.0 x 0.5 master block, each with 2*kappa
+    elements along its long edges and kappa along the short one, the faces
+    opposite the interface clamped, an initial overlap of 0.001, E = 10 and
+    nu = 0.3, and multipliers in the standard (linear Lagrange) basis.  The
+    paper's material is Neo-Hooke; this is its linearisation at rest."""
     return make_contact_problem(
         3,
         (2 * kappa, 2 * kappa, kappa),
@@ -489,4 +511,9 @@ def weak_scaling_problem(kappa: int, seed: int = 0) -> ContactProblem:
         slave_box=([0.1, 0.1, 0.0], [0.8, 0.8, 0.4]),
         master_box=([0.0, 0.0, -0.5], [1.0, 1.0, 0.5]),
         seed=seed,
+        top_bc="clamped",
+        rhs=rhs,
+        lm_basis=lm_basis,
+        E=10.0,
+        penetration=0.001,
     )

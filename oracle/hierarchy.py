@@ -206,8 +206,12 @@ def lagmult_aggregation(disp_agg, n_disp_agg, slave_dofs, Gmat, bs_u, lm_node, n
     Walks the slave displacement dofs i in ascending order; k is the
     aggregate of i's node; every multiplier j coupled to i (a stored entry
     G[i, j], i.e. D_ij != 0 with D^T held in G's slave rows) puts j's
-    pseudo-node into the multiplier aggregate d(k), created on first
-    encounter.  A pseudo-node keeps its first assignment.
+    pseudo-node into the multiplier aggregate d(k).  A pseudo-node keeps its
+    first assignment, and d(k) is created when the first pseudo-node is put
+    into it: with a non-diagonal D an aggregate whose multipliers were all
+    claimed before gets none (an empty multiplier aggregate would have no
+    null-space rows).  With a dual (diagonal) D this is the order of first
+    encounter.
     Returns (lm_agg per pseudo-node, dmap per displacement aggregate, count).
     """
     lm_agg = np.full(n_lm_nodes, -1, dtype=np.int64)
@@ -218,11 +222,11 @@ def lagmult_aggregation(disp_agg, n_disp_agg, slave_dofs, Gmat, bs_u, lm_node, n
         if k < 0:
             continue
         for j in Gmat.indices[Gmat.indptr[i]:Gmat.indptr[i + 1]]:
-            if dmap[k] < 0:
-                dmap[k] = n_l
-                n_l += 1
             nl = lm_node[j]
             if lm_agg[nl] < 0:
+                if dmap[k] < 0:
+                    dmap[k] = n_l
+                    n_l += 1
                 lm_agg[nl] = dmap[k]
     return lm_agg, dmap, n_l
 

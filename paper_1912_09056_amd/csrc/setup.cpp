@@ -16,7 +16,10 @@
 //    smallest id); remaining nodes seed aggregates with their free
 //    neighbours.
 //  * Alg. 1: slave displacement dofs in ascending order, "D_ij != 0" is a
-//    stored entry of G's slave row; a pseudo-node keeps its first aggregate.
+//    stored entry of G's slave row; a pseudo-node keeps its first aggregate,
+//    and a multiplier aggregate is created with its first member (with a
+//    non-diagonal D an aggregate whose multipliers were all claimed earlier
+//    gets none).
 //  * Tentative transfers: per-aggregate modified Gram-Schmidt QR of the
 //    null-space rows (ascending dof order, columns in order, R_kk > 0); the
 //    pattern of P holds all n_ns coarse columns of the aggregate for every
@@ -240,9 +243,10 @@ int64_t lagmult_aggregation(const HostLevel& L, std::vector<int32_t>& agg_l) {
       int32_t k = L.agg_u[node];
       if (k < 0) continue;
       for (int64_t e = L.G.rp[i]; e < L.G.rp[i + 1]; ++e) {
-        if (dmap[k] < 0) dmap[k] = (int32_t)count++;
-        int32_t pn = L.lm_node[L.G.ci[e]];
-        if (agg_l[pn] < 0) agg_l[pn] = dmap[k];
+        const int32_t pn = L.lm_node[L.G.ci[e]];
+        if (agg_l[pn] >= 0) continue;  // first assignment wins
+        if (dmap[k] < 0) dmap[k] = (int32_t)count++;  // created with its first member
+        agg_l[pn] = dmap[k];
       }
     }
   }

@@ -213,3 +213,62 @@ def test_curved_interface_small():
     A = p.full_matrix().tocsc()
     x = sp.linalg.spsolve(A, p.b)
     assert np.linalg.norm(A @ x - p.b) < 1e-10 * np.linalg.norm(p.b)
+
+
+# ---- standard (non-dual) multiplier basis and the weak-scaling problem ----
+
+
+def test_mortar_1d_standard_basis_closed_form():
+    # linear Lagrange functions: D is the 1D mass matrix h/6 [1 4 1]
+    # (h/3 on the end nodes), symmetric positive definite, with row sums
+    # int N_j (the dual D's diagonal); matching meshes give M = D, and full
+    # master coverage gives M row sums int N_j too
+    h = 0.125
+    xs = np.arange(9) * h
+    D, M = mortar_1d(xs, xs, basis="standard")
+    ref = np.diag(np.full(9, 4.0)) + np.diag(np.ones(8), 1) + np.diag(np.ones(8), -1)
+    ref[0, 0] = ref[-1, -1] = 2.0
+    assert np.allclose(D, ref * h / 6, rtol=0, atol=1e-15)
+    assert np.allclose(M, D, rtol=0, atol=1e-15)
+    Dd, _ = mortar_1d(xs, xs)
+    assert np.allclose(D.sum(axis=1), Dd, rtol=0, atol=1e-15)
+    assert np.linalg.eigvalsh(D).min() > 0
+    xm = np.linspace(-0.05, 1.07, 12)  # non-matching, covers the slave line
+    D2, M2 = mortar_1d(xs, xm, basis="standard")
+    assert np.allclose(M2.sum(axis=1), Dd, rtol=0, atol=1e-14)
+    assert np.allclose(D2, D, rtol=0, atol=1e-15)
+
+
+def test_standard_basis_face_and_blocks():
+    p = make_contact_problem(3, (4, 4, 2), (5, 5, 2), lm_basis="standard", top_bc="clamped", rhs="gap",
+                             penetration=0.001)
+    q = make_contact_problem(3, (4, 4, 2), (5, 5, 2), top_bc="clamped", rhs="gap", penetration=0.001)
+    # G slave rows now couple a slave dof to up to 9 multipliers of its component
+    Gs = p.G[p.slave_dofs].tocsr()
+    assert np.diff(Gs.indptr).max() == 9 and np.diff(q.G[q.slave_dofs].tocsr().indptr).max() == 1
+    # the two bases give the same weighted gap (row sums of D are int N_j)
+    assert np.allclose(p.b, q.b, rtol=0, atol=1e-15)
+    d = p.dim
+    normal_rows = p.n_u + np.arange(p.n_lam // d) * d + (d - 1)
+    assert np.all(p.b[normal_rows] > 0) and np.count_nonzero(p.b) == normal_rows.size
+    # constraint rows equal the matching rows of G^T (normal slot)
+    Bn = p.B[normal_rows - p.n_u].toarray()
+    GT = p.G.T.tocsr()[normal_rows - p.n_u].toarray()
+    assert np.allclose(Bn, GT, rtol=0, atol=1e-15)
+
+
+def test_weak_scaling_problem_closes_the_overlap():
+    # direct solve of the linearised weak-scaling problem: the slave face
+    # moves away from the master by the overlap (weighted), both clamped
+    # blocks are compressed
+    import scipy.sparse.linalg as spl
+
+    p = weak_scaling_problem(2)
+    x = spl.spsolve(p.full_matrix().tocsc(), p.b)
+    u = x[: p.n_u]
+    d = p.dim
+    s_nodes = p.slave_dofs[d - 1::d] // d
+    m_nodes = p.master_dofs[d - 1::d] // d
+    assert np.all(u[s_nodes * d + d - 1] > 0) and np.all(u[m_nodes * d + d - 1] < 0)
+    normal_rows = np.arange(p.n_lam // d) * d + (d - 1)
+    assert np.allclose(p.B[normal_rows] @ u, p.b[p.n_u + normal_rows], rtol=1e-9, atol=0)

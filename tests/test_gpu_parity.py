@@ -363,6 +363,51 @@ def test_simple_coarse_solver_converges():
             assert abs(info["iters"] - ref.iters) <= 1
 
 
+# (oracle options, library options, fixed-iteration parity): with the
+# default diagonal Schur step the standard basis makes the smoother a poor
+# preconditioner (the diagonal of S is no convergent splitting when D is
+# not diagonal), FGMRES stagnates for its first iterations and a
+# fixed-iteration comparison there only measures rounding; the l1 Schur
+# sweeps fix that
+STANDARD_VARIANTS = [
+    ({}, {}, False),
+    (dict(schur="l1", schur_sweeps=4), dict(schur=1, schur_sweeps=4), True),
+    (dict(prolongator="sa", nu_pre=3, nu_post=3, jacobi_sweeps=2, schur="l1", schur_sweeps=8),
+     dict(prolongator=1, nu_pre=3, nu_post=3, jacobi_sweeps=2, schur=1, schur_sweeps=8), True),
+]
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_standard_basis_weak_scaling(fmt):
+    """Weak-scaling problem with standard multipliers (non-diagonal D), three
+    levels: V-cycle and transpose (FP64 1e-12, mixed 2e-5) and both
+    precisions solving to 1e-8 for default, l1-Schur and weak-scaling-like
+    settings; fixed-iteration FGMRES against the oracle where FGMRES is well
+    conditioned."""
+    from contactgen import weak_scaling_problem
+
+    prob = weak_scaling_problem(4)
+    A = prob.full_matrix()
+    r = np.random.default_rng(18).standard_normal(prob.n)
+    for okw, lkw, fixed in STANDARD_VARIANTS:
+        kw = dict(max_levels=3, max_coarse_rows=200)
+        oopts = OracleOptions(**kw, **okw)
+        lv = build_hierarchy(prob, oopts)
+        for prec, tol in ((0, 1e-12), (1, 2e-5)):
+            s = _solver(prob, precision=prec, fmt=fmt, **kw, **lkw)
+            for tr in (False, True):
+                z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+                assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < tol, (okw, prec, tr)
+            x, info = s.solve(torch.from_numpy(prob.b), rtol=1e-8, max_iters=500)
+            assert info["converged"], (okw, prec, info)
+            assert np.linalg.norm(prob.b - A @ x.cpu().numpy()) <= 1.0001e-8 * np.linalg.norm(prob.b)
+        if fixed:
+            s = _solver(prob, fmt=fmt, **kw, **lkw)
+            ref = oracle_solve(lv, oopts, prob.b, m=20, fixed_iters=30)
+            x, info = s.solve(torch.from_numpy(prob.b), m=20, fixed_iters=30)
+            assert _rel(x.cpu().numpy(), ref.x) < 1e-10, okw
+
+
 def test_bench_workload_parity():
     """The 40^3 / 41x41x40 workload at full size, in the launch configuration the
     benchmark times: V-cycle (FP64) against the oracle on a seeded vector, and both

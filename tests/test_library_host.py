@@ -194,3 +194,26 @@ def test_simple_coarse_solver_host_setup():
         with pytest.raises(CamgError) as e:
             AMGSolver.from_problem(p, AMGOptions(max_levels=2, **bad), host_only=True)
         assert e.value.code == -1, bad
+
+
+@pytest.mark.parametrize("kappa,levels", [(3, 3), (6, 3)])
+def test_host_hierarchy_standard_basis_matches_oracle(kappa, levels):
+    # weak-scaling problem with the standard multiplier basis (non-diagonal
+    # D): Alg. 1's first-assignment rule bit for bit, every level's blocks
+    # and transfers with identical patterns, values to rounding
+    from contactgen import weak_scaling_problem
+
+    prob = weak_scaling_problem(kappa)
+    ora, lib = _pair(prob, max_levels=levels, max_coarse_rows=100)
+    assert lib.n_levels == len(ora) == levels
+    for l, L in enumerate(ora):
+        blocks = ["K", "G", "B", "C"] + (["P_u", "P_l"] if l + 1 < len(ora) else [])
+        for blk in blocks:
+            A = lib.level_matrix(l, blk)
+            R = getattr(L, blk)
+            assert np.array_equal(A.indptr, R.indptr) and np.array_equal(A.indices, R.indices), (l, blk)
+            scale = max(1.0, np.abs(R.data).max()) if R.nnz else 1.0
+            assert np.abs(A.data - R.data).max(initial=0.0) <= 1e-13 * scale, (l, blk)
+        if l + 1 < len(ora):
+            du, dl = lib.aggregates(l)
+            assert np.array_equal(du, L.agg_u) and np.array_equal(dl, L.agg_l), l

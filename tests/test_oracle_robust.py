@@ -197,3 +197,51 @@ def test_simple_coarse_solver_needs_no_factorisation():
         build_hierarchy(p, AMGOptions(max_levels=3, max_coarse_rows=10))
     lv = build_hierarchy(p, AMGOptions(max_levels=3, max_coarse_rows=10, coarse_solver="simple"))
     assert len(lv) == 3 and lv[-1].A_inv is None and lv[-1].sd_inv is not None
+
+
+# ---- standard (non-dual) multiplier basis: Alg. 1 with a non-diagonal D ----
+
+
+@pytest.mark.parametrize("kappa", [2, 3])
+def test_alg1_first_assignment_with_nondiagonal_D(kappa):
+    # brute force of the rule: a multiplier pseudo-node joins the aggregate
+    # d(k) of the first slave dof (ascending) that couples to it, so two
+    # pseudo-nodes share a multiplier aggregate exactly when their first
+    # coupled slave dofs lie in the same displacement aggregate; no
+    # multiplier aggregate is empty
+    from contactgen import weak_scaling_problem
+
+    p = weak_scaling_problem(kappa)
+    L = build_hierarchy(p, AMGOptions(max_levels=2, max_coarse_rows=50))[0]
+    G = L.G.tocsc()
+    first = {}
+    for j in range(L.n_l):
+        rows = G.indices[G.indptr[j]:G.indptr[j + 1]]
+        assert rows.size > 1 or kappa == 0  # D is not diagonal
+        pn = L.lm_node[j]
+        i = rows.min()
+        first[pn] = min(first.get(pn, i), i)
+    key = {pn: L.agg_u[i // L.bs_u] for pn, i in first.items()}
+    pns = sorted(first)
+    for a in pns:
+        for b in pns:
+            assert (L.agg_l[a] == L.agg_l[b]) == (key[a] == key[b])
+    counts = np.bincount(L.agg_l)
+    assert counts.min() > 0 and counts.size == L.agg_l.max() + 1
+
+
+def test_standard_basis_hierarchy_and_solve():
+    from contactgen import weak_scaling_problem
+
+    p = weak_scaling_problem(3)
+    for o in (AMGOptions(max_levels=3, max_coarse_rows=100),
+              AMGOptions(max_levels=3, max_coarse_rows=100, prolongator="sa", nu_pre=3, nu_post=3)):
+        lv = build_hierarchy(p, o)
+        assert len(lv) == 3
+        rng = np.random.default_rng(17)
+        x, y = rng.standard_normal(p.n), rng.standard_normal(p.n)
+        a1 = y @ vcycle(lv, x, o)
+        a2 = vcycle(lv, y, o, transpose=True) @ x
+        assert abs(a1 - a2) <= 1e-12 * abs(a1)
+        r = solve(lv, o, p.b, rtol=1e-8, max_iters=400)
+        assert r.converged and r.rel_res_true <= 1e-8
