@@ -71,6 +71,7 @@ class AMGOptions:
     schur_sweeps: int = 1  # Jacobi sweeps on the Schur system (1 = divide by the diagonal)
     coarse_solver: str = "lu"  # coarsest level: "lu" (merged dense LU) or "simple" (CheapSIMPLE sweeps)
     coarse_sweeps: int = 2  # sweeps from zero on the coarsest level with "simple"
+    smoother: str = "simple"  # block smoother: "simple" (CheapSIMPLE), "uzawa", "braess_sarazin"
 
 
 @dataclass
@@ -372,6 +373,18 @@ def smoother_data(L: Level, opts: AMGOptions):
     L.dinv = At_inv.copy() if opts.jacobi_diag == "atilde" else 1.0 / dK
     L.atilde_inv = At_inv
     L.sd_inv = 1.0 / Sd
+    if opts.smoother == "braess_sarazin":
+        # S_a = B Atilde^-1 G / alpha - C (Sec. 5.1.2), same diagonal rule
+        Sa = schur_matrix(L, At_inv / opts.simple_alpha)
+        if opts.schur == "l1":
+            da = np.sign(Sa.diagonal()) * np.asarray(abs(Sa).sum(axis=1)).ravel()
+        else:
+            da = Sa.diagonal()
+        if np.any(da == 0.0):
+            raise ZeroDivisionError("zero Schur diagonal")
+        L.extra["bs_sd_inv"] = 1.0 / da
+        if opts.schur_sweeps > 1:
+            L.extra["bs_S"] = Sa
 
 
 class SingularCoarse(np.linalg.LinAlgError):

@@ -79,6 +79,87 @@ def cheap_simple_sweep(L, b, z, omega, alpha, jac_sweeps=1, predict=None, schur_
     return out
 
 
+def cheap_uzawa_sweep(L, b, z, omega, alpha, jac_sweeps=1, schur_sweeps=1, predict=None, schur_solve=None):
+    """One inexact Uzawa sweep (Sec. 5.1.1, Alg. 2) with the cheap inverses:
+    prediction w = J(r_u) (Jacobi sweeps on K), multiplier increment
+    delta = -S^-1 (r_l - B w) with the SIMPLE Schur approximation
+    S = B Atilde^-1 G - C, both updates damped by alpha and no
+    back-substitution into the displacements (the one-way coupling of the
+    Uzawa matrix).  predict / schur_solve replace the cheap inverses when
+    given (exact solves for the paper's error-matrix statement)."""
+    n_u = L.n_u
+    zu, zl = z[:n_u], z[n_u:]
+    ru = b[:n_u] - (L.K @ zu + L.G @ zl)
+    rl = b[n_u:] - (L.B @ zu + L.C @ zl)
+    w = jacobi(L.K, L.dinv, ru, omega, jac_sweeps) if predict is None else predict(ru)
+    rt = rl - L.B @ w
+    delta = -schur_apply(L, rt, schur_sweeps) if schur_solve is None else -schur_solve(rt)
+    out = np.empty_like(z)
+    out[:n_u] = zu + alpha * w
+    out[n_u:] = zl + alpha * delta
+    return out
+
+
+def cheap_uzawa_sweep_adjoint(L, b, z, omega, alpha, jac_sweeps=1, KT=None, schur_sweeps=1):
+    """Transpose of the Uzawa sweep map: delta = -S^-T s_l,
+    z_l += alpha delta, z_u += alpha J^T (s_u - B^T delta)."""
+    n_u = L.n_u
+    KT = L.K.T.tocsr() if KT is None else KT
+    zu, zl = z[:n_u], z[n_u:]
+    su = b[:n_u] - (KT @ zu + L.B.T @ zl)
+    sl = b[n_u:] - (L.G.T @ zu + L.C.T @ zl)
+    delta = -schur_apply(L, sl, schur_sweeps, transpose=True)
+    out = np.empty_like(z)
+    out[n_u:] = zl + alpha * delta
+    out[:n_u] = zu + alpha * jacobi(KT, L.dinv, su - L.B.T @ delta, omega, jac_sweeps)
+    return out
+
+
+def braess_sarazin_sweep(L, b, z, alpha, schur_sweeps=1, schur_solve=None):
+    """One cheap Braess-Sarazin sweep (Sec. 5.1.2, Alg. 3) with the damping
+    alpha and the easy-to-invert Ahat = Atilde:
+      u_half = u + Ahat^-1 r_u / alpha
+      delta  = -S_a^-1 (b_l - B u_half - C lam),  S_a = B Ahat^-1 G / alpha - C
+      lam   += delta,  u = u_half - Ahat^-1 G delta / alpha.
+    S_a's data (diagonal, optional matrix) is kept in L.extra; schur_solve
+    replaces the cheap Schur inverse when given."""
+    n_u = L.n_u
+    zu, zl = z[:n_u], z[n_u:]
+    ru = b[:n_u] - (L.K @ zu + L.G @ zl)
+    u_half = zu + L.atilde_inv * ru / alpha
+    rt = b[n_u:] - (L.B @ u_half + L.C @ zl)
+    delta = -_bs_schur(L, rt, schur_sweeps, False) if schur_solve is None else -schur_solve(rt)
+    out = np.empty_like(z)
+    out[n_u:] = zl + delta
+    out[:n_u] = u_half - L.atilde_inv * (L.G @ delta) / alpha
+    return out
+
+
+def braess_sarazin_sweep_adjoint(L, b, z, alpha, schur_sweeps=1, KT=None):
+    """Transpose of the Braess-Sarazin sweep map:
+    delta = -S_a^-T (s_l - G^T Ahat^-1 s_u / alpha), lam += delta,
+    u += Ahat^-1 (s_u - B^T delta) / alpha."""
+    n_u = L.n_u
+    KT = L.K.T.tocsr() if KT is None else KT
+    zu, zl = z[:n_u], z[n_u:]
+    su = b[:n_u] - (KT @ zu + L.B.T @ zl)
+    sl = b[n_u:] - (L.G.T @ zu + L.C.T @ zl)
+    delta = -_bs_schur(L, sl - L.G.T @ (L.atilde_inv * su) / alpha, schur_sweeps, True)
+    out = np.empty_like(z)
+    out[n_u:] = zl + delta
+    out[:n_u] = zu + L.atilde_inv * (su - L.B.T @ delta) / alpha
+    return out
+
+
+def _bs_schur(L, rt, sweeps, transpose):
+    if sweeps <= 1:
+        return rt * L.extra["bs_sd_inv"]
+    key = "bs_ST" if transpose else "bs_S"
+    if key not in L.extra:
+        L.extra["bs_ST"] = L.extra["bs_S"].T.tocsr()
+    return jacobi(L.extra[key], L.extra["bs_sd_inv"], rt, 1.0, sweeps)
+
+
 def cheap_simple_sweep_adjoint(L, b, z, omega, alpha, jac_sweeps=1, KT=None, schur_sweeps=1):
     n_u = L.n_u
     KT = L.K.T.tocsr() if KT is None else KT

@@ -21,7 +21,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .smoother import cheap_simple_sweep, cheap_simple_sweep_adjoint
+from .smoother import (braess_sarazin_sweep, braess_sarazin_sweep_adjoint, cheap_simple_sweep,
+                       cheap_simple_sweep_adjoint, cheap_uzawa_sweep, cheap_uzawa_sweep_adjoint)
 
 
 def _apply_A(L, z, transpose):
@@ -43,12 +44,22 @@ def vcycle(levels, b, opts, level=0, transpose=False):
         KT = L.K.T.tocsr()
 
         def sweep(bb, zz):
+            if opts.smoother == "uzawa":
+                return cheap_uzawa_sweep_adjoint(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps,
+                                                 KT, schur_sweeps=opts.schur_sweeps)
+            if opts.smoother == "braess_sarazin":
+                return braess_sarazin_sweep_adjoint(L, bb, zz, opts.simple_alpha, opts.schur_sweeps, KT)
             return cheap_simple_sweep_adjoint(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps, KT,
                                               schur_sweeps=opts.schur_sweeps)
     else:
         n_pre, n_post = opts.nu_pre, opts.nu_post
 
         def sweep(bb, zz):
+            if opts.smoother == "uzawa":
+                return cheap_uzawa_sweep(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps,
+                                         schur_sweeps=opts.schur_sweeps)
+            if opts.smoother == "braess_sarazin":
+                return braess_sarazin_sweep(L, bb, zz, opts.simple_alpha, opts.schur_sweeps)
             return cheap_simple_sweep(L, bb, zz, opts.jacobi_omega, opts.simple_alpha, opts.jacobi_sweeps,
                                       schur_sweeps=opts.schur_sweeps)
 
