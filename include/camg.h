@@ -101,6 +101,9 @@ typedef struct {
 #define CAMG_SCHUR_L1 1          /* ... signed l1 row sums of that matrix   */
 #define CAMG_COARSE_LU 0         /* coarsest level: merged dense LU inverse */
 #define CAMG_COARSE_SIMPLE 1     /* ... CheapSIMPLE sweeps from zero        */
+#define CAMG_SMOOTHER_SIMPLE 0   /* block smoother: CheapSIMPLE (Alg. 3 of Sec. 5.1.3) */
+#define CAMG_SMOOTHER_UZAWA 1    /* inexact Uzawa (Sec. 5.1.1, Alg. 2)      */
+#define CAMG_SMOOTHER_BRAESS_SARAZIN 2 /* cheap Braess-Sarazin (Sec. 5.1.2) */
 typedef struct {
   int32_t max_levels;      /* >= 1; 1 = direct solve of the whole system  */
   int32_t max_coarse_rows; /* stop coarsening at or below this many rows   */
@@ -112,7 +115,7 @@ typedef struct {
   int32_t spmv_format;     /* CAMG_SPMV_* (storage of K on device)         */
   int32_t graphs;          /* 1: capture the V-cycle once into a HIP graph and replay it */
   double jacobi_omega;     /* Jacobi damping                               */
-  double simple_alpha;     /* SIMPLE damping (Alg. 3)                      */
+  double simple_alpha;     /* block damping alpha (Alg. 3; see smoother), > 0 */
   /* Robustness settings for strong stiffness contrast (defaults keep the
    * plain method):
    * prolongator: CAMG_PROLONG_SMOOTHED smooths the displacement transfers,
@@ -134,6 +137,14 @@ typedef struct {
    * factorisation, so a singular coarsest matrix is no error. */
   int32_t coarse_solver;   /* CAMG_COARSE_*                                */
   int32_t coarse_sweeps;   /* 1..64                                        */
+  /* Block smoother of every smoothing level (and of the CheapSIMPLE coarse
+   * solver).  simple_alpha is its block damping alpha in all three cases
+   * (the paper's CheapSIMPLE(0.8), CheapUzawa(0.7), CheapBraessSarazin(1.9)):
+   * Uzawa damps both updates by alpha and has no back-substitution;
+   * Braess-Sarazin predicts with one step of the lumped diagonal scaled by
+   * alpha (jacobi_omega and jacobi_sweeps are not used) and solves with
+   * S_a = B Atilde^-1 G / alpha - C. */
+  int32_t smoother;        /* CAMG_SMOOTHER_*                              */
 } amg_options;
 
 /* FGMRES options. */

@@ -77,6 +77,7 @@ class amg_options(Structure):
         ("sa_omega", c_double),
         ("coarse_solver", c_int32),
         ("coarse_sweeps", c_int32),
+        ("smoother", c_int32),
     ]
 
 
@@ -207,6 +208,7 @@ class AMGOptions:
     sa_omega: float = 4.0 / 3.0
     coarse_solver: int = 0  # coarsest level: 0 dense LU inverse, 1 CheapSIMPLE sweeps
     coarse_sweeps: int = 2
+    smoother: int = 0  # 0 CheapSIMPLE, 1 inexact Uzawa, 2 cheap Braess-Sarazin (simple_alpha is the block damping)
 
     def to_c(self) -> amg_options:
         o = amg_options()

@@ -246,7 +246,10 @@ __global__ void __launch_bounds__(kBlock) k_tsmooth_l(DCSR<T> GT, DCSR<T> CT, co
   const int lane = threadIdx.x % SG;
   if (row >= n_l) return;
   T gz = T(0), gs = T(0), cz = T(0);
-  if (GT.nnz) row_dot2<T, SG>(GT, zu, ainv, su, row, lane, gz, gs);
+  if (GT.nnz) {
+    if (ainv) row_dot2<T, SG>(GT, zu, ainv, su, row, lane, gz, gs);
+    else if (!FIRST) gz = row_dot<T, SG>(GT, zu, row, lane);
+  }
   if (!FIRST && CT.nnz) cz = row_dot<T, SG>(CT, zl, row, lane);
   gz = sg_reduce<T, SG>(gz);
   gs = sg_reduce<T, SG>(gs);
@@ -290,6 +293,15 @@ __global__ void __launch_bounds__(kBlock) k_tcorrect_u(DCSR<T> BT, const T* __re
     t_out[i] = t;
     w_out[i] = w;
   }
+}
+
+// Uzawa update of the displacements: zn_u = z_u + alpha w (z_u null: zero).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_uzawa_update(const T* __restrict__ zu, const T* __restrict__ w, T alpha,
+                                                         T* __restrict__ znu, int n_u) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_u) return;
+  znu[i] = (zu ? zu[i] : T(0)) + alpha * w[i];
 }
 
 template <typename T>
@@ -1011,6 +1023,13 @@ void tcorrect_u(const DCSR<T>& BT, const T* su, const T* delta, const T* jinv, T
 }
 
 template <typename T>
+void uzawa_update(const T* zu, const T* w, T alpha, T* znu, int n_u, hipStream_t s) {
+  if (n_u <= 0) return;
+  k_uzawa_update<T><<<grid_for(n_u, kBlock), kBlock, 0, s>>>(zu, w, alpha, znu, n_u);
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
 void dense_gemv(const T* M, const T* x, T* y, int n, hipStream_t s) {
   if (n <= 0) return;
   k_dense_gemv<T><<<grid_for(n, kBlock / 64), kBlock, 0, s>>>(M, x, y, n);
@@ -1305,6 +1324,7 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
   template void tcorrect_u<T>(const DCSR<T>&, const T*, const T*, const T*, T, T, const T*, T*, T*, T*, int, bool,  \
                               hipStream_t);                                                                        \
   template void dense_gemv<T>(const T*, const T*, T*, int, hipStream_t);                                           \
+  template void uzawa_update<T>(const T*, const T*, T, T*, int, hipStream_t);                                      \
   template void copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                                   \
   template void zero_vec<T>(T*, int64_t, hipStream_t);                                                             \
   template void scatter_perm<T>(const double*, const int32_t*, T*, int64_t, hipStream_t);                          \

@@ -71,7 +71,8 @@ void tsmooth_u(const DCSR<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, c
                bool first, int sg, hipStream_t s);
 
 // Adjoint sweep, step 2: s_l = b_l - G^T z_u - C^T z_l,
-// delta = -(s_l - G^T (ainv .* s_u)) * sdinv, zn_l = z_l + alpha * delta;
+// delta = -(s_l - G^T (ainv .* s_u)) * sdinv, zn_l = z_l + alpha * delta
+// (ainv null: no G^T ainv s_u term, the adjoint Uzawa sweep);
 // rhs_out (optional) receives q = -(s_l - G^T (ainv .* s_u)).
 template <typename T>
 void tsmooth_l(const DCSR<T>& GT, const DCSR<T>& CT, const T* zu, const T* zl, const T* bl, const T* su,
@@ -110,6 +111,10 @@ void op_apply_from_f32(const DBELL<double>& K, const DCSR<double>& A12, const DC
 void op_apply_copy(const DBELL<double>& K, const DCSR<double>& A12, const DCSR<double>& A21,
                    const DCSR<double>& A22, const double* x, double* y, double* xcopy, int n1, int n2,
                    hipStream_t s);
+
+// Uzawa update of the displacements: zn_u = z_u + alpha w (z_u null: zero).
+template <typename T>
+void uzawa_update(const T* zu, const T* w, T alpha, T* znu, int n_u, hipStream_t s);
 
 // y = M x for a dense row-major n x n matrix (coarsest level).
 template <typename T>

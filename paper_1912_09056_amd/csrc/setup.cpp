@@ -32,6 +32,8 @@
 //    Atilde = diag(sum_j |K_ij|), whose bound lambda(Atilde^-1 K) <= 1 lets
 //    the printed omega = 4/3 be used as is; pattern = P_tent's plus the
 //    symbolic pattern of K P_tent.
+//  * Braess-Sarazin (Sec. 5.1.2, Alg. 3) with damping alpha maps onto the
+//    CheapSIMPLE data with the lumping alpha * Ahat (see smoother_data).
 //  * Optional CheapSIMPLE coarse solver (the weak-scaling study's second
 //    coarse-solver variant): smoother data on the coarsest level too, no
 //    merged matrix and no factorisation.
@@ -507,6 +509,15 @@ void smoother_data(HostLevel& L, const SetupOptions& opt) {
     if (dg[i] == 0.0) fail(kErrZeroDiag, "zero diagonal entry in K");
     double a = opt.atilde == 0 ? at[i] : dg[i];
     if (a == 0.0) fail(kErrZeroDiag, "zero SIMPLEC lumping");
+    if (opt.bs_alpha > 0.0) {
+      // Braess-Sarazin with damping alpha is the CheapSIMPLE sweep with the
+      // lumping alpha * Ahat, unit dampings and that lumping as the
+      // prediction's diagonal: its Schur matrix is B Ahat^-1 G / alpha - C
+      a *= opt.bs_alpha;
+      L.atilde_inv[i] = 1.0 / a;
+      L.jac_inv[i] = 1.0 / a;
+      continue;
+    }
     L.atilde_inv[i] = 1.0 / a;
     L.jac_inv[i] = opt.jacobi_diag == 0 ? 1.0 / a : 1.0 / dg[i];
   }

@@ -59,6 +59,9 @@ struct SetupOptions {
   int schur = 0;         // 0 diagonal of S, 1 signed l1 row sums of S
   int schur_sweeps = 1;  // > 1: keep S for Jacobi sweeps
   bool simple_coarse = false;  // coarsest level smooths (smoother data, no dense inverse)
+  // Braess-Sarazin: > 0 scales the lumping to lumping * bs_alpha, which then
+  // also serves as the prediction's diagonal (the sweep runs with unit dampings)
+  double bs_alpha = 0.0;
 };
 
 // Status codes mirror the C-ABI's CAMG_* values.

@@ -465,8 +465,16 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   DevLevel& D = h.lev[l];
   LevelVecs<T>& V = vecs<T>(D);
   const int nu = (int)D.n_u, nl = (int)D.n_l;
-  const T om = (T)h.opts.jacobi_omega, al = (T)h.opts.simple_alpha;
-  const int nj = std::max(1, h.opts.jacobi_sweeps);
+  // Braess-Sarazin runs the CheapSIMPLE kernels on its scaled lumping with
+  // unit dampings and one Jacobi step (the setup folded its damping in);
+  // Uzawa keeps the prediction w for its damped displacement update and
+  // skips the back-substitution
+  const bool uzawa = h.opts.smoother == CAMG_SMOOTHER_UZAWA;
+  const bool bsz = h.opts.smoother == CAMG_SMOOTHER_BRAESS_SARAZIN;
+  const T om = bsz ? T(1) : (T)h.opts.jacobi_omega;
+  const T al = bsz ? T(1) : (T)h.opts.simple_alpha;
+  const int nj = bsz ? 1 : std::max(1, h.opts.jacobi_sweeps);
+  const bool keep_w = nj > 1 || uzawa;
   const int ks = D.S.nrows > 0 ? std::max(1, h.opts.schur_sweeps) - 1 : 0;  // Jacobi sweeps on S after the first
   T* q = ks ? V.qrhs.p : nullptr;
   const T* bu = b;
@@ -480,18 +488,21 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
     smooth_first_l<T>(D.B.view<T>(), bu, bl, V.jinv.p, V.sdinv.p, om, al, znl, V.delta.p, q, nl, s);
     const T* dfin = schur_steps<T>(D.S.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, nullptr, al, znl, ks, nl,
                                    D.sg_S, s);
-    smooth_first_u<T>(D.G.view<T>(), bu, V.jinv.p, V.ainv.p, dfin, om, al, znu, nu, s);
+    if (uzawa)  // zn_u = alpha * omega * jinv .* b_u: no back-substitution
+      smooth_first_u<T>(DCSR<T>{}, bu, V.jinv.p, V.ainv.p, dfin, al * om, al, znu, nu, s);
+    else
+      smooth_first_u<T>(D.G.view<T>(), bu, V.jinv.p, V.ainv.p, dfin, om, al, znu, nu, s);
     return;
   }
   if (!transpose) {
     {
       ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
       if (D.bell && !first)
-        smooth_u_bell<T>(D.Kb.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, nj > 1 ? V.aux1.p : nullptr,
-                         nj > 1 ? V.aux2.p : nullptr, nu, s);
+        smooth_u_bell<T>(D.Kb.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, keep_w ? V.aux1.p : nullptr,
+                         keep_w ? V.aux2.p : nullptr, nu, s);
       else
-        smooth_u<T>(D.K.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, nj > 1 ? V.aux1.p : nullptr,
-                    nj > 1 ? V.aux2.p : nullptr, nu, first, D.sg_K, s);
+        smooth_u<T>(D.K.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, keep_w ? V.aux1.p : nullptr,
+                    keep_w ? V.aux2.p : nullptr, nu, first, D.sg_K, s);
     }
     T* wa = V.aux2.p;
     T* wb = V.su.p;
@@ -507,7 +518,10 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
     smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, V.sdinv.p, al, znl, V.delta.p, q, nl, first, s);
     const T* dfin = schur_steps<T>(D.S.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, first ? nullptr : zl, al,
                                    znl, ks, nl, D.sg_S, s);
-    correct_u<T>(D.G.view<T>(), D.g_rows.p, D.n_g_rows, dfin, V.ainv.p, al, znu, s);
+    if (uzawa)
+      uzawa_update<T>(first ? nullptr : zu, wa, al, znu, nu, s);
+    else
+      correct_u<T>(D.G.view<T>(), D.g_rows.p, D.n_g_rows, dfin, V.ainv.p, al, znu, s);
   } else {
     // from z = 0 the adjoint residual is b itself: no first kernel
     const T* su = first ? bu : V.su.p;
@@ -518,12 +532,12 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
       else
         tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, false, D.sg_K, s);
     }
-    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, su, V.ainv.p, V.sdinv.p, al, znl, V.delta.p, q, nl,
-                 first, s);
+    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, su, uzawa ? nullptr : V.ainv.p, V.sdinv.p, al, znl,
+                 V.delta.p, q, nl, first, s);
     const T* dfin = schur_steps<T>(D.ST.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, first ? nullptr : zl, al,
                                    znl, ks, nl, D.sg_S, s);
-    tcorrect_u<T>(D.BT.view<T>(), su, dfin, V.jinv.p, om, al, zu, znu, nj > 1 ? V.aux1.p : nullptr,
-                  nj > 1 ? V.aux2.p : nullptr, nu, first, s);
+    tcorrect_u<T>(D.BT.view<T>(), su, dfin, V.jinv.p, om, uzawa ? T(1) : al, zu, znu, keep_w ? V.aux1.p : nullptr,
+                  keep_w ? V.aux2.p : nullptr, nu, first, s);
     T* wa = V.aux2.p;
     T* wb = V.r.p;  // r is free during a sweep
     for (int k = 1; k < nj; ++k) {
@@ -535,6 +549,7 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
                         D.sg_K, s);
       std::swap(wa, wb);
     }
+    if (uzawa) uzawa_update<T>(first ? nullptr : zu, wa, al, znu, nu, s);
   }
 }
 
@@ -911,6 +926,7 @@ void amg_default_options(amg_options* o) {
   o->sa_omega = 4.0 / 3.0;
   o->coarse_solver = CAMG_COARSE_LU;
   o->coarse_sweeps = 2;
+  o->smoother = CAMG_SMOOTHER_SIMPLE;
 }
 
 void amg_default_gmres_options(amg_gmres_options* o) {
@@ -937,7 +953,8 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
       o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
       o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 1 || o.schur_sweeps < 1 ||
       o.schur_sweeps > 64 || !(o.sa_omega > 0.0) || !std::isfinite(o.sa_omega) || o.coarse_solver < 0 ||
-      o.coarse_solver > 1 || o.coarse_sweeps < 1 || o.coarse_sweeps > 64)
+      o.coarse_solver > 1 || o.coarse_sweeps < 1 || o.coarse_sweeps > 64 || o.smoother < 0 || o.smoother > 2 ||
+      !(o.simple_alpha > 0.0) || !std::isfinite(o.simple_alpha))
     api_fail(CAMG_ERR_INVALID_ARG, "invalid options");
   const int64_t nu = p->K.nrows, nl = p->C.nrows;
   if (nu <= 0 || nu % p->dim) api_fail(CAMG_ERR_SHAPE, "n_u must be a positive multiple of dim");
@@ -1008,6 +1025,7 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   so.schur = o.schur;
   so.schur_sweeps = o.schur_sweeps;
   so.simple_coarse = o.coarse_solver == CAMG_COARSE_SIMPLE;
+  so.bs_alpha = o.smoother == CAMG_SMOOTHER_BRAESS_SARAZIN ? o.simple_alpha : 0.0;
   build_hierarchy(h->host, so);
   return h;
 }

@@ -408,6 +408,52 @@ def test_standard_basis_weak_scaling(fmt):
             assert _rel(x.cpu().numpy(), ref.x) < 1e-10, okw
 
 
+# (oracle options, library options): the paper's block smoothers
+BLOCK_SMOOTHERS = [
+    (dict(smoother="uzawa", simple_alpha=0.7), dict(smoother=1, simple_alpha=0.7)),
+    (dict(smoother="uzawa", simple_alpha=0.7, jacobi_sweeps=2, schur="l1", schur_sweeps=3),
+     dict(smoother=1, simple_alpha=0.7, jacobi_sweeps=2, schur=1, schur_sweeps=3)),
+    (dict(smoother="braess_sarazin", simple_alpha=1.9), dict(smoother=2, simple_alpha=1.9)),
+]
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+@pytest.mark.parametrize("which", range(len(BLOCK_SMOOTHERS)))
+def test_uzawa_and_braess_sarazin(fmt, which):
+    """Inexact Uzawa and cheap Braess-Sarazin sweeps: V-cycle and its
+    transpose (FP64 1e-12, mixed 2e-5) and fixed-iteration FGMRES against the
+    oracle on a three-level 2D hierarchy (three sweeps per level, as in the
+    paper's smoother comparison), and a converged 3D solve."""
+    okw, lkw = BLOCK_SMOOTHERS[which]
+    prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=19)
+    kw = dict(max_levels=3, max_coarse_rows=50, nu_pre=3, nu_post=3)
+    oopts = OracleOptions(**kw, **okw)
+    lv = build_hierarchy(prob, oopts)
+    r = np.random.default_rng(20).standard_normal(prob.n)
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        s = _solver(prob, precision=prec, fmt=fmt, **kw, **lkw)
+        for tr in (False, True):
+            z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+            assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < tol, (okw, prec, tr)
+    s = _solver(prob, fmt=fmt, **kw, **lkw)
+    for tr in (False, True):
+        ref = oracle_solve(lv, oopts, prob.b, transpose=tr, m=10, fixed_iters=20)
+        x, info = s.solve(torch.from_numpy(prob.b), transpose=tr, m=10, fixed_iters=20)
+        assert _rel(x.cpu().numpy(), ref.x) < 1e-10, (okw, tr)
+    p3 = make_workload("contact3d_6")
+    A = p3.full_matrix()
+    o3 = OracleOptions(max_levels=2, nu_pre=3, nu_post=3, **okw)
+    ref = oracle_solve(build_hierarchy(p3, o3), o3, p3.b, rtol=1e-8, max_iters=500)
+    for prec in (0, 1):
+        s = _solver(p3, precision=prec, fmt=fmt, max_levels=2, nu_pre=3, nu_post=3, **lkw)
+        x, info = s.solve(torch.from_numpy(p3.b), rtol=1e-8, max_iters=500)
+        print(f"[block-smoother] {okw} prec={prec} iters={info['iters']} oracle={ref.iters}", flush=True)
+        assert info["converged"], (okw, prec, info)
+        assert np.linalg.norm(p3.b - A @ x.cpu().numpy()) <= 1.0001e-8 * np.linalg.norm(p3.b)
+        if prec == 0:
+            assert abs(info["iters"] - ref.iters) <= 1
+
+
 def test_bench_workload_parity():
     """The 40^3 / 41x41x40 workload at full size, in the launch configuration the
     benchmark times: V-cycle (FP64) against the oracle on a seeded vector, and both
