@@ -517,3 +517,51 @@ def weak_scaling_problem(kappa: int, seed: int = 0, lm_basis: str = "standard", 
         E=10.0,
         penetration=0.001,
     )
+
+
+def rotate_problem(p: ContactProblem, angle_y: float, angle_z: float) -> ContactProblem:
+    """The same contact problem with the whole geometry rotated by R =
+    R_z(angle_z) R_y(angle_y) (radians), as in the rotation experiment of
+    the two-body example (Sec. 6.1 experimental setup).  Displacements and
+    the Cartesian multipliers rotate with R node by node; the constraint rows
+    (normal gap, tangential slots) are scalar equations and do not:
+        K' = Q K Q^T, G' = Q G Ql^T, B' = B Q^T, C' = C Ql^T,
+        b' = [Q b_u; b_l],
+    so the solution is [Q u; Ql l].  Dirichlet rows stay identity rows only
+    where whole nodes are clamped (top_bc="clamped")."""
+    cy, sy, cz, sz = np.cos(angle_y), np.sin(angle_y), np.cos(angle_z), np.sin(angle_z)
+    Ry = np.array([[cy, 0.0, sy], [0.0, 1.0, 0.0], [-sy, 0.0, cy]])
+    Rz = np.array([[cz, -sz, 0.0], [sz, cz, 0.0], [0.0, 0.0, 1.0]])
+    R = Rz @ Ry
+    d = p.dim
+    assert d == 3
+    d_nodes = p.dirichlet.reshape(-1, d)
+    if np.any(d_nodes.any(axis=1) & ~d_nodes.all(axis=1)):
+        raise ValueError("rotation needs whole nodes clamped (top_bc='clamped')")
+    Q = sp.kron(sp.identity(p.n_u // d), sp.csr_matrix(R), format="csr")
+    Ql = sp.kron(sp.identity(p.n_lam // d), sp.csr_matrix(R), format="csr")
+
+    def clean(M):
+        M = sp.csr_matrix(M)
+        M.eliminate_zeros()
+        M.sort_indices()
+        return M
+
+    b = p.b.copy()
+    b[: p.n_u] = Q @ p.b[: p.n_u]
+    return ContactProblem(
+        dim=d,
+        K=clean(Q @ p.K @ Q.T),
+        G=clean(Q @ p.G @ Ql.T),
+        B=clean(p.B @ Q.T),
+        C=clean(p.C @ Ql.T),
+        b=b,
+        slave_dofs=p.slave_dofs,
+        master_dofs=p.master_dofs,
+        lm_node=p.lm_node,
+        nullspace=np.asarray(Q @ p.nullspace),
+        coords=p.coords @ R.T,
+        dirichlet=p.dirichlet,
+        top_dofs=p.top_dofs,
+        info=dict(p.info, rotation=(angle_y, angle_z)),
+    )

@@ -272,3 +272,28 @@ def test_weak_scaling_problem_closes_the_overlap():
     assert np.all(u[s_nodes * d + d - 1] > 0) and np.all(u[m_nodes * d + d - 1] < 0)
     normal_rows = np.arange(p.n_lam // d) * d + (d - 1)
     assert np.allclose(p.B[normal_rows] @ u, p.b[p.n_u + normal_rows], rtol=1e-9, atol=0)
+
+
+def test_rotated_problem_has_the_rotated_solution():
+    # rotating the geometry rotates displacements and Cartesian multipliers
+    # node by node and leaves the constraint equations: the direct solution
+    # of the rotated system is [Q u; Ql lam]
+    import scipy.sparse.linalg as spl
+
+    from contactgen import rotate_problem
+
+    p = make_contact_problem(3, (4, 4, 3), (5, 5, 3), top_bc="clamped", rhs="random", seed=3)
+    x = spl.spsolve(p.full_matrix().tocsc(), p.b)
+    ay, az = np.pi / 8, 3 * np.pi / 8
+    q = rotate_problem(p, ay, az)
+    xr = spl.spsolve(q.full_matrix().tocsc(), q.b)
+    cy, sy, cz, sz = np.cos(ay), np.sin(ay), np.cos(az), np.sin(az)
+    R = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1.0]]) @ np.array([[cy, 0, sy], [0, 1.0, 0], [-sy, 0, cy]])
+    expect = np.concatenate([(x[: p.n_u].reshape(-1, 3) @ R.T).ravel(), (x[p.n_u:].reshape(-1, 3) @ R.T).ravel()])
+    assert np.linalg.norm(xr - expect) <= 1e-10 * np.linalg.norm(expect)
+    # rigid-body modes of the rotated bodies are in K's kernel away from the clamps
+    KZ = np.abs(q.K @ q.nullspace).max(axis=1)
+    free = ~q.dirichlet
+    assert np.sort(KZ[free])[free.sum() // 2] <= 1e-12 * np.abs(q.K.data).max()
+    with pytest.raises(ValueError):
+        rotate_problem(make_contact_problem(3, (2, 2, 2), (3, 3, 2)), 0.1, 0.2)  # roller: partial clamps
