@@ -67,7 +67,7 @@ class AMGOptions:
     jacobi_diag: str = "atilde"  # relaxation diagonal of the prediction: "atilde" or "diag"
     prolongator: str = "pa"  # displacement transfers: "pa" tentative, "sa" smoothed
     sa_omega: float = 4.0 / 3.0  # prolongator smoothing factor (with the lumped diagonal)
-    schur: str = "diag"  # diagonal of the Schur approximation: "diag" or "l1"
+    schur: str = "diag"  # relaxation of the Schur approximation: "diag", "l1" or "block" (nodal blocks)
     schur_sweeps: int = 1  # Jacobi sweeps on the Schur system (1 = divide by the diagonal)
     coarse_solver: str = "lu"  # coarsest level: "lu" (merged dense LU) or "simple" (CheapSIMPLE sweeps)
     coarse_sweeps: int = 2  # sweeps from zero on the coarsest level with "simple"
@@ -346,7 +346,13 @@ def smoother_data(L: Level, opts: AMGOptions):
     which bound the spectrum of diag^-1 S by one for symmetric positive
     semi-definite S (as Atilde does for K), so Jacobi sweeps on the Schur
     system converge even where the mortar coupling M dominates D (a much
-    softer master side).  With schur_sweeps > 1 the matrix itself is kept."""
+    softer master side).  "block" relaxes with the inverses of S's nodal
+    diagonal blocks (the d multipliers of one node): with Cartesian
+    multipliers and normal/tangential constraint rows a node's block of S
+    mixes all its components once the interface normal leaves the
+    coordinate axes, and its diagonal alone can vanish (a rigidly rotated
+    problem), while the block transforms with the rotation.  With
+    schur_sweeps > 1 the matrix itself is kept."""
     dK = L.K.diagonal()
     if np.any(dK == 0.0):
         raise ZeroDivisionError("zero diagonal in K")
@@ -358,7 +364,14 @@ def smoother_data(L: Level, opts: AMGOptions):
         raise ZeroDivisionError("zero Atilde")
     At_inv = 1.0 / At
     # diag(B Atilde^-1 G)_j = sum_i B[j, i] G[i, j] / Atilde_i
-    if opts.schur == "l1" or opts.schur_sweeps > 1:
+    L.extra.pop("sb_inv", None)
+    L.extra.pop("bs_sb_inv", None)
+    if opts.schur == "block":
+        S = schur_matrix(L, At_inv)
+        L.extra["sb_inv"] = node_block_inverse(S, L.bs_l, L.lm_node)
+        Sd = S.diagonal()
+        L.S = S if opts.schur_sweeps > 1 else None
+    elif opts.schur == "l1" or opts.schur_sweeps > 1:
         S = schur_matrix(L, At_inv)
         if opts.schur == "l1":
             Sd = np.sign(S.diagonal()) * np.asarray(abs(S).sum(axis=1)).ravel()
@@ -368,14 +381,20 @@ def smoother_data(L: Level, opts: AMGOptions):
     else:
         BG = L.B.multiply(L.G.T.tocsr()).tocsr()
         Sd = np.asarray(BG @ At_inv).ravel() - L.C.diagonal()
-    if np.any(Sd == 0.0):
+    if opts.schur != "block" and np.any(Sd == 0.0):
         raise ZeroDivisionError("zero Schur diagonal")
     L.dinv = At_inv.copy() if opts.jacobi_diag == "atilde" else 1.0 / dK
     L.atilde_inv = At_inv
-    L.sd_inv = 1.0 / Sd
+    L.sd_inv = None if opts.schur == "block" else 1.0 / Sd
     if opts.smoother == "braess_sarazin":
         # S_a = B Atilde^-1 G / alpha - C (Sec. 5.1.2), same diagonal rule
         Sa = schur_matrix(L, At_inv / opts.simple_alpha)
+        if opts.schur == "block":
+            L.extra["bs_sb_inv"] = node_block_inverse(Sa, L.bs_l, L.lm_node)
+            L.extra.pop("bs_sd_inv", None)
+            if opts.schur_sweeps > 1:
+                L.extra["bs_S"] = Sa
+            return
         if opts.schur == "l1":
             da = np.sign(Sa.diagonal()) * np.asarray(abs(Sa).sum(axis=1)).ravel()
         else:
@@ -385,6 +404,27 @@ def smoother_data(L: Level, opts: AMGOptions):
         L.extra["bs_sd_inv"] = 1.0 / da
         if opts.schur_sweeps > 1:
             L.extra["bs_S"] = Sa
+
+
+def node_block_inverse(S, bs, lm_node=None):
+    """Inverses of the bs x bs diagonal blocks of S over multiplier nodes
+    (bs consecutive dofs each): shape (n_l / bs, bs, bs).  The nodal block
+    Jacobi relaxation of the Schur system (block option) divides by these."""
+    n = S.shape[0]
+    if bs <= 0 or n % bs:
+        raise ValueError("multiplier count is not a multiple of the node block size")
+    if lm_node is not None and len(lm_node) and not np.array_equal(np.asarray(lm_node), np.arange(n) // bs):
+        raise ValueError("block Schur relaxation needs node-contiguous multipliers")
+    Sd = S.toarray() if n <= 4096 else None
+    out = np.empty((n // bs, bs, bs))
+    for j in range(n // bs):
+        sl = slice(j * bs, (j + 1) * bs)
+        blk = Sd[sl, sl] if Sd is not None else S[sl, sl].toarray()
+        try:
+            out[j] = np.linalg.inv(blk)
+        except np.linalg.LinAlgError:
+            raise ZeroDivisionError(f"singular Schur node block {j}") from None
+    return out
 
 
 class SingularCoarse(np.linalg.LinAlgError):

@@ -33,7 +33,13 @@ A^T = [[K^T, B^T], [G^T, C^T]]:
 
 J^T is the same Jacobi polynomial taken with K^T; with Schur sweeps the
 division by S_d becomes the same number of Jacobi sweeps on S^T (the
-transpose of sum_i (I - D^-1 S)^i D^-1 is sum_i (I - D^-1 S^T)^i D^-1).
+transpose of sum_i (I - D^-1 S)^i D^-1 is sum_i (I - D^-T S^T)^i D^-T).
+
+Block option: D is the block diagonal of S over multiplier nodes (the d
+Cartesian components of one slave node, or of one coarse multiplier
+aggregate), so the correction solves a small dense system per node instead
+of dividing per row; the transposed sweep relaxes S^T with the transposed
+blocks.
 """
 from __future__ import annotations
 
@@ -48,18 +54,48 @@ def jacobi(K, dinv, r, omega, sweeps):
     return w
 
 
+def node_block_solve(blk_inv, r, transpose=False):
+    """Per multiplier node j (bs consecutive dofs): blk_inv[j] @ r_j, or
+    blk_inv[j]^T @ r_j with transpose (the inverse of the transposed block)."""
+    nb, bs, _ = blk_inv.shape
+    out = np.empty(nb * bs)
+    for j in range(nb):
+        Mj = blk_inv[j].T if transpose else blk_inv[j]
+        out[j * bs:(j + 1) * bs] = Mj @ r[j * bs:(j + 1) * bs]
+    return out
+
+
+def _schur_relax(S_of, d_inv, blk_inv, rt, sweeps, transpose):
+    """`sweeps` undamped Jacobi sweeps from zero on S delta = rt (S^T with
+    transpose), relaxing with the diagonal d_inv or, when blk_inv is given,
+    with the nodal diagonal blocks (block Jacobi); one sweep is the division
+    (block solve) alone."""
+    if blk_inv is not None:
+        relax = lambda v: node_block_solve(blk_inv, v, transpose)  # noqa: E731
+    else:
+        relax = lambda v: v * d_inv  # noqa: E731
+    if sweeps <= 1:
+        return relax(rt)
+    S = S_of()
+    x = np.zeros_like(rt)
+    for _ in range(sweeps):
+        x = x + relax(rt - S @ x)
+    return x
+
+
 def schur_apply(L, rt, sweeps, transpose=False):
     """Approximate solve of S delta = rt: division by the stored diagonal
-    (one sweep) or `sweeps` undamped Jacobi sweeps from zero on S (S^T)."""
-    if sweeps <= 1:
-        return rt * L.sd_inv
-    if transpose:
+    (by the nodal blocks with the block option) for one sweep, else `sweeps`
+    undamped (block) Jacobi sweeps from zero on S (S^T)."""
+
+    def S_of():
+        if not transpose:
+            return L.S
         if "ST" not in L.extra:
             L.extra["ST"] = L.S.T.tocsr()
-        S = L.extra["ST"]
-    else:
-        S = L.S
-    return jacobi(S, L.sd_inv, rt, 1.0, sweeps)
+        return L.extra["ST"]
+
+    return _schur_relax(S_of, L.sd_inv, L.extra.get("sb_inv"), rt, sweeps, transpose)
 
 
 def cheap_simple_sweep(L, b, z, omega, alpha, jac_sweeps=1, predict=None, schur_solve=None, schur_sweeps=1):
@@ -152,12 +188,14 @@ def braess_sarazin_sweep_adjoint(L, b, z, alpha, schur_sweeps=1, KT=None):
 
 
 def _bs_schur(L, rt, sweeps, transpose):
-    if sweeps <= 1:
-        return rt * L.extra["bs_sd_inv"]
-    key = "bs_ST" if transpose else "bs_S"
-    if key not in L.extra:
-        L.extra["bs_ST"] = L.extra["bs_S"].T.tocsr()
-    return jacobi(L.extra[key], L.extra["bs_sd_inv"], rt, 1.0, sweeps)
+    def S_of():
+        if not transpose:
+            return L.extra["bs_S"]
+        if "bs_ST" not in L.extra:
+            L.extra["bs_ST"] = L.extra["bs_S"].T.tocsr()
+        return L.extra["bs_ST"]
+
+    return _schur_relax(S_of, L.extra.get("bs_sd_inv"), L.extra.get("bs_sb_inv"), rt, sweeps, transpose)
 
 
 def cheap_simple_sweep_adjoint(L, b, z, omega, alpha, jac_sweeps=1, KT=None, schur_sweeps=1):
