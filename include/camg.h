@@ -99,6 +99,7 @@ typedef struct {
 #define CAMG_PROLONG_SMOOTHED 1  /* ... smoothed aggregation (SA)           */
 #define CAMG_SCHUR_DIAG 0        /* Schur diagonal: diag(B Atilde^-1 G - C) */
 #define CAMG_SCHUR_L1 1          /* ... signed l1 row sums of that matrix   */
+#define CAMG_SCHUR_BLOCK 2       /* ... its nodal diagonal blocks (block Jacobi) */
 #define CAMG_COARSE_LU 0         /* coarsest level: merged dense LU inverse */
 #define CAMG_COARSE_SIMPLE 1     /* ... CheapSIMPLE sweeps from zero        */
 #define CAMG_SMOOTHER_SIMPLE 0   /* block smoother: CheapSIMPLE (Alg. 3 of Sec. 5.1.3) */
@@ -125,7 +126,14 @@ typedef struct {
    *   tentative.
    * schur / schur_sweeps: the correction step solves S delta = -r with
    *   S = B Atilde^-1 G - C by schur_sweeps undamped Jacobi sweeps from zero
-   *   (1 = division by the diagonal), the diagonal chosen by CAMG_SCHUR_*. */
+   *   (1 = division by the diagonal), the diagonal chosen by CAMG_SCHUR_*.
+   *   CAMG_SCHUR_BLOCK relaxes with the inverses of S's diagonal blocks over
+   *   multiplier nodes (the bs_l multipliers of one node, consecutive; the
+   *   problem's lm_node must map multiplier j to node j / dim): with Cartesian
+   *   multipliers the normal and tangential constraint rows of a node mix its
+   *   components wherever the interface normal is not a coordinate axis, and
+   *   the diagonal alone can vanish there (the rotated two-body experiment of
+   *   Sec. 6.1).  A singular node block is CAMG_ERR_ZERO_DIAG. */
   int32_t prolongator;     /* CAMG_PROLONG_*                               */
   int32_t schur;           /* CAMG_SCHUR_*                                 */
   int32_t schur_sweeps;    /* 1..64                                        */
@@ -204,7 +212,9 @@ int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out);
 int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_t* lm_agg);
 
 /* Copies block `which` (0=K, 1=G, 2=B, 3=C, 4=P_u, 5=P_l, 6=S, the Schur
- * matrix B Atilde^-1 G - C kept when schur_sweeps > 1, else 0 x 0) of
+ * matrix B Atilde^-1 G - C kept when schur_sweeps > 1, else 0 x 0; 7=the
+ * inverse nodal blocks of S as a block-diagonal matrix with CAMG_SCHUR_BLOCK,
+ * else 0 x 0) of
  * `level` to host arrays in FP64 (rowptr: nrows+1, col/val: nnz).  Call with
  * NULL arrays to query *nrows, *ncols, *nnz first. */
 int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols,

@@ -203,8 +203,8 @@ class AMGOptions:
     jacobi_omega: float = 0.8
     simple_alpha: float = 0.8
     prolongator: int = 0  # 0 tentative, 1 smoothed aggregation (displacement transfers)
-    schur: int = 0  # Schur diagonal: 0 diag(S), 1 signed l1 row sums
-    schur_sweeps: int = 1  # Jacobi sweeps on the Schur system (1 = division by the diagonal)
+    schur: int = 0  # Schur relaxation: 0 diag(S), 1 signed l1 row sums, 2 nodal diagonal blocks of S
+    schur_sweeps: int = 1  # (block) Jacobi sweeps on the Schur system (1 = division by the diagonal / blocks)
     sa_omega: float = 4.0 / 3.0
     coarse_solver: int = 0  # coarsest level: 0 dense LU inverse, 1 CheapSIMPLE sweeps
     coarse_sweeps: int = 2
@@ -325,11 +325,13 @@ class AMGSolver:
         return du, dl
 
     def level_matrix(self, level: int, which: str):
-        """Host copy of block K/G/B/C/P_u/P_l/S of a level as scipy CSR (S:
-        the Schur matrix, kept only with schur_sweeps > 1, else 0 x 0)."""
+        """Host copy of block K/G/B/C/P_u/P_l/S/Sblk_inv of a level as scipy
+        CSR (S: the Schur matrix, kept only with schur_sweeps > 1; Sblk_inv:
+        the inverse nodal blocks of S with the block Schur option; else
+        0 x 0)."""
         import scipy.sparse as sp
 
-        w = {"K": 0, "G": 1, "B": 2, "C": 3, "P_u": 4, "P_l": 5, "S": 6}[which]
+        w = {"K": 0, "G": 1, "B": 2, "C": 3, "P_u": 4, "P_l": 5, "S": 6, "Sblk_inv": 7}[which]
         nr, nc, nz = c_int64(), c_int64(), c_int64()
         _check(self.lib.amg_get_level_matrix(self.handle, level, w, byref(nr), byref(nc), byref(nz), None, None, None))
         rp = np.zeros(nr.value + 1, np.int64)

@@ -10,6 +10,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <stdexcept>
 
 namespace camg {
 
@@ -199,8 +200,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_l(DCSR<T> B, DCSR<T> C, const
   s = sg_reduce<T, SG>(s);
   if (lane == 0) {
     const T q = -(bl[row] - s);
-    const T d = q * sdinv[row];
     if (rhs_out) rhs_out[row] = q;
+    if (!sdinv) return;  // block option: the nodal step divides
+    const T d = q * sdinv[row];
     delta[row] = d;
     znl[row] = (FIRST ? T(0) : zl[row]) + alpha * d;
   }
@@ -257,8 +259,9 @@ __global__ void __launch_bounds__(kBlock) k_tsmooth_l(DCSR<T> GT, DCSR<T> CT, co
   if (lane == 0) {
     const T sl = FIRST ? bl[row] : bl[row] - gz - cz;
     const T q = -(sl - gs);
-    const T d = q * sdinv[row];
     if (rhs_out) rhs_out[row] = q;
+    if (!sdinv) return;
+    const T d = q * sdinv[row];
     delta[row] = d;
     znl[row] = (FIRST ? T(0) : zl[row]) + alpha * d;
   }
@@ -363,8 +366,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_l_first(DCSR<T> B, const T* _
   s = sg_reduce<T, SG>(s);
   if (lane == 0) {
     const T q = -(bl[row] - s);
-    const T d = q * sdinv[row];
     if (rhs_out) rhs_out[row] = q;
+    if (!sdinv) return;
+    const T d = q * sdinv[row];
     delta[row] = d;
     znl[row] = alpha * d;
   }
@@ -387,6 +391,38 @@ __global__ void __launch_bounds__(kBlock) k_schur_jacobi(DCSR<T> S, const T* __r
     const T dn = d_in[row] + sdinv[row] * (q[row] - s);
     d_out[row] = dn;
     if (last) znl[row] = (zl ? zl[row] : T(0)) + alpha * dn;
+  }
+}
+
+// One step of nodal block Jacobi on the Schur system S delta = q (block
+// option), one thread per multiplier node j (BS consecutive rows):
+//   d_out_j = d_in_j + M_j (q_j - (S d_in)_j),   d_in null: d_out_j = M_j q_j,
+// M_j the inverse of S's j-th diagonal block (row-major), applied transposed
+// with TRANS for the S^T system (S passed as S^T then).  On the last step
+// also zn_l = z_l + alpha * d_out (z_l null: zero).
+template <typename T, int BS, bool TRANS>
+__global__ void __launch_bounds__(kBlock) k_schur_block(DCSR<T> S, const T* __restrict__ q,
+                                                        const T* __restrict__ d_in, const T* __restrict__ blk,
+                                                        T* __restrict__ d_out, const T* __restrict__ zl, T alpha,
+                                                        T* __restrict__ znl, int last, int n_nodes) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n_nodes) return;
+  T r[BS];
+#pragma unroll
+  for (int a = 0; a < BS; ++a) {
+    const int row = j * BS + a;
+    r[a] = q[row];
+    if (d_in) r[a] -= csr_row_serial<T>(S, d_in, row);
+  }
+  const T* M = blk + (size_t)j * (BS * BS);
+#pragma unroll
+  for (int a = 0; a < BS; ++a) {
+    const int row = j * BS + a;
+    T d = d_in ? d_in[row] : T(0);
+#pragma unroll
+    for (int b = 0; b < BS; ++b) d += (TRANS ? M[b * BS + a] : M[a * BS + b]) * r[b];
+    d_out[row] = d;
+    if (last) znl[row] = (zl ? zl[row] : T(0)) + alpha * d;
   }
 }
 
@@ -969,6 +1005,37 @@ T* schur_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* sdinv, con
 }
 
 template <typename T>
+T* schur_block_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* blk, bool trans, const T* zl, T alpha,
+                     T* znl, int steps, int n_l, int bs, hipStream_t s) {
+  if (n_l <= 0 || steps <= 0) return d_a;
+  if (bs < 1 || bs > 3 || n_l % bs) throw std::runtime_error("block Schur step: node block size must be 1..3");
+  const int nn = n_l / bs;
+  const T* din = nullptr;
+  T* dout = d_a;
+  for (int k = 0; k < steps; ++k) {
+    const int last = (k == steps - 1) ? 1 : 0;
+    const unsigned g = grid_for(nn, kBlock);
+#define CAMG_SCHUR_BLOCK_LAUNCH(BSV)                                                                          \
+  if (trans)                                                                                                  \
+    k_schur_block<T, BSV, true><<<g, kBlock, 0, s>>>(S, q, din, blk, dout, zl, alpha, znl, last, nn);          \
+  else                                                                                                        \
+    k_schur_block<T, BSV, false><<<g, kBlock, 0, s>>>(S, q, din, blk, dout, zl, alpha, znl, last, nn);
+    if (bs == 3) {
+      CAMG_SCHUR_BLOCK_LAUNCH(3)
+    } else if (bs == 2) {
+      CAMG_SCHUR_BLOCK_LAUNCH(2)
+    } else {
+      CAMG_SCHUR_BLOCK_LAUNCH(1)
+    }
+#undef CAMG_SCHUR_BLOCK_LAUNCH
+    CAMG_LAUNCHED();
+    din = dout;
+    dout = (dout == d_a) ? d_b : d_a;
+  }
+  return const_cast<T*>(din);
+}
+
+template <typename T>
 void correct_u(const DCSR<T>& G, const int32_t* rows, int n_rows, const T* delta, const T* ainv, T alpha, T* znu,
                hipStream_t s) {
   if (n_rows <= 0) return;
@@ -1316,6 +1383,8 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
                             int, bool, hipStream_t);                                                               \
   template T* schur_steps<T>(const DCSR<T>&, const T*, T*, T*, const T*, const T*, T, T*, int, int, int,          \
                              hipStream_t);                                                                         \
+  template T* schur_block_steps<T>(const DCSR<T>&, const T*, T*, T*, const T*, bool, const T*, T, T*, int, int, int, \
+                                   hipStream_t);                                                                   \
   template void correct_u<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, hipStream_t);         \
   template void tsmooth_u<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, T*, int, bool, int,      \
                              hipStream_t);                                                                         \

@@ -59,6 +59,14 @@ void smooth_l(const DCSR<T>& B, const DCSR<T>& C, const T* znu, const T* zl, con
 template <typename T>
 T* schur_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* sdinv, const T* zl, T alpha, T* znl,
                int steps, int n_l, int sg, hipStream_t s);
+// Nodal block Jacobi steps on the Schur system (block option): steps >= 1,
+// the first from zero; blk holds the inverse bs x bs diagonal blocks of S
+// (row-major), applied transposed with trans (S passed as S^T then).  The
+// last step writes zn_l = z_l + alpha * delta; returns the buffer holding
+// delta.
+template <typename T>
+T* schur_block_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* blk, bool trans, const T* zl, T alpha,
+                     T* znl, int steps, int n_l, int bs, hipStream_t s);
 
 // zn_u[i] -= alpha * ainv[i] * (G delta)[i] for the listed rows of G.
 template <typename T>

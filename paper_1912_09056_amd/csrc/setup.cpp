@@ -123,6 +123,7 @@ void append_blocks(HostCSR& out, std::vector<RowBlock>& blocks) {
   }
 }
 
+constexpr int kErrShape = -2;
 constexpr int kErrZeroDiag = -4;
 constexpr int kErrRankDeficient = -5;
 constexpr int kErrSingularCoarse = -6;
@@ -522,6 +523,49 @@ void smoother_data(HostLevel& L, const SetupOptions& opt) {
     L.jac_inv[i] = opt.jacobi_diag == 0 ? 1.0 / a : 1.0 / dg[i];
   }
   L.sd_inv.resize((size_t)nl);
+  L.sblk_inv.clear();
+  if (opt.schur == 2) {
+    // nodal block Jacobi: inverses of S's bs_l x bs_l diagonal blocks (the
+    // multipliers of one node are consecutive)
+    const int bs = L.bs_l;
+    if (bs <= 0 || bs > 3 || nl % bs) fail(kErrShape, "multiplier count is not a multiple of the node block size");
+    for (int64_t j = 0; j < (int64_t)L.lm_node.size(); ++j)
+      if (L.lm_node[(size_t)j] != j / bs) fail(kErrShape, "block Schur relaxation needs node-contiguous multipliers");
+    HostCSR S = schur_matrix(L);
+    L.sblk_inv.assign((size_t)(nl * bs), 0.0);
+    for (int64_t nd = 0; nd < nl / bs; ++nd) {
+      double a[4][8] = {};
+      for (int r = 0; r < bs; ++r) {
+        const int64_t j = nd * bs + r;
+        for (int64_t k = S.rp[j]; k < S.rp[j + 1]; ++k) {
+          const int64_t c = S.ci[k] - nd * bs;
+          if (c >= 0 && c < bs) a[r][c] = S.v[k];
+        }
+        a[r][bs + r] = 1.0;
+      }
+      // Gauss-Jordan with partial pivoting on [A | I]
+      for (int c = 0; c < bs; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < bs; ++r)
+          if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+        if (a[piv][c] == 0.0) fail(kErrZeroDiag, "singular Schur node block");
+        if (piv != c)
+          for (int k = 0; k < 2 * bs; ++k) std::swap(a[c][k], a[piv][k]);
+        const double inv = 1.0 / a[c][c];
+        for (int k = 0; k < 2 * bs; ++k) a[c][k] *= inv;
+        for (int r = 0; r < bs; ++r) {
+          if (r == c || a[r][c] == 0.0) continue;
+          const double f = a[r][c];
+          for (int k = 0; k < 2 * bs; ++k) a[r][k] -= f * a[c][k];
+        }
+      }
+      for (int r = 0; r < bs; ++r)
+        for (int c = 0; c < bs; ++c) L.sblk_inv[(size_t)((nd * bs + r) * bs + c)] = a[r][bs + c];
+    }
+    for (int64_t j = 0; j < nl; ++j) L.sd_inv[(size_t)j] = 0.0;  // unused: the blocks relax
+    if (opt.schur_sweeps > 1) L.S = std::move(S);
+    return;
+  }
   if (opt.schur == 1 || opt.schur_sweeps > 1) {
     HostCSR S = schur_matrix(L);
     for (int64_t j = 0; j < nl; ++j) {

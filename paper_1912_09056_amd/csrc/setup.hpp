@@ -41,6 +41,7 @@ struct HostLevel {
   int64_t n_agg_u = 0, n_agg_l = 0;
   HostCSR P_u, P_l;
   std::vector<double> atilde_inv, jac_inv, sd_inv;
+  std::vector<double> sblk_inv;    // block Schur option: inverse nodal blocks, bs_l x bs_l row-major each
   HostCSR S;                       // B Atilde^-1 G - C (only when relaxed by Jacobi sweeps)
   std::vector<double> Ainv;        // coarsest level with the direct solve: dense inverse, row-major
   int64_t n_u() const { return K.nrows; }
@@ -56,7 +57,7 @@ struct SetupOptions {
   int jacobi_diag = 0;  // 0 Atilde, 1 diag(K)
   int prolongator = 0;  // 0 tentative, 1 smoothed (displacement transfers)
   double sa_omega = 4.0 / 3.0;
-  int schur = 0;         // 0 diagonal of S, 1 signed l1 row sums of S
+  int schur = 0;         // 0 diagonal of S, 1 signed l1 row sums of S, 2 nodal blocks of S
   int schur_sweeps = 1;  // > 1: keep S for Jacobi sweeps
   bool simple_coarse = false;  // coarsest level smooths (smoother data, no dense inverse)
   // Braess-Sarazin: > 0 scales the lumping to lumping * bs_alpha, which then

@@ -186,6 +186,7 @@ struct LevelVecs {
   DBuf<T> b, z, zn, r, delta, aux1, aux2, su;
   DBuf<T> delta2, qrhs;  // Schur sweeps: second delta buffer and right-hand side
   DBuf<T> jinv, ainv, sdinv;
+  DBuf<T> sblk;  // block Schur option: inverse nodal blocks of S (bs_l x bs_l, row-major)
   DBuf<T> Ainv, AinvT;
 };
 
@@ -194,6 +195,7 @@ struct DevLevel {
   DevMat K, G, B, C, KT, GT, BT, CT, Pu, Pl, Ru, Rl;
   DevMat S, ST;  // Schur matrix B Atilde^-1 G - C and its transpose (Schur sweeps only)
   int sg_S = 8;
+  int sblk_bs = 0;     // > 0: the Schur step relaxes with nodal blocks of this size
   bool bell = false;   // K and K^T in sliced blocked-ELL layout
   DevBell Kb, KTb;
   int64_t k_blocks = 0, k_slots = 0;
@@ -353,6 +355,7 @@ static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool dense_coarse, h
     up(V.jinv, H.jac_inv);
     up(V.ainv, H.atilde_inv);
     up(V.sdinv, H.sd_inv);
+    if (!H.sblk_inv.empty()) up(V.sblk, H.sblk_inv);
   } else {
     up(V.Ainv, H.Ainv);
     std::vector<double> t(H.Ainv.size());
@@ -432,6 +435,7 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       D.n_g_rows = (int32_t)gr.size();
       D.g_rows.upload(gr, s);
     }
+    D.sblk_bs = (!dense_coarse && !H.sblk_inv.empty()) ? H.bs_l : 0;
     if (mixed) alloc_vecs<float>(D.v32, H, dense_coarse, s);
     else alloc_vecs<double>(D.v64, H, dense_coarse, s);
     if (mixed && l == 0) {
@@ -476,7 +480,17 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   const int nj = bsz ? 1 : std::max(1, h.opts.jacobi_sweeps);
   const bool keep_w = nj > 1 || uzawa;
   const int ks = D.S.nrows > 0 ? std::max(1, h.opts.schur_sweeps) - 1 : 0;  // Jacobi sweeps on S after the first
-  T* q = ks ? V.qrhs.p : nullptr;
+  // block option: the multiplier kernels only write the right-hand side
+  // q = -(r_l - B w) and the nodal block steps form delta and zn_l
+  const bool sblock = D.sblk_bs > 0;
+  T* q = (ks || sblock) ? V.qrhs.p : nullptr;
+  const T* sdv = sblock ? nullptr : V.sdinv.p;
+  auto schur = [&](const DevMat& SM, const T* zl_in, bool trans) -> const T* {
+    if (sblock)
+      return schur_block_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sblk.p, trans, zl_in, al, zn + nu, ks + 1,
+                                  nl, D.sblk_bs, s);
+    return schur_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, zl_in, al, zn + nu, ks, nl, D.sg_S, s);
+  };
   const T* bu = b;
   const T* bl = b + nu;
   const T* zu = z;
@@ -485,9 +499,8 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   T* znl = zn + nu;
   Prof* pp = (l == 0) ? &h.prof : nullptr;
   if (!transpose && first && nj == 1) {
-    smooth_first_l<T>(D.B.view<T>(), bu, bl, V.jinv.p, V.sdinv.p, om, al, znl, V.delta.p, q, nl, s);
-    const T* dfin = schur_steps<T>(D.S.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, nullptr, al, znl, ks, nl,
-                                   D.sg_S, s);
+    smooth_first_l<T>(D.B.view<T>(), bu, bl, V.jinv.p, sdv, om, al, znl, V.delta.p, q, nl, s);
+    const T* dfin = schur(D.S, nullptr, false);
     if (uzawa)  // zn_u = alpha * omega * jinv .* b_u: no back-substitution
       smooth_first_u<T>(DCSR<T>{}, bu, V.jinv.p, V.ainv.p, dfin, al * om, al, znu, nu, s);
     else
@@ -515,9 +528,8 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
                         D.sg_K, s);
       std::swap(wa, wb);
     }
-    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, V.sdinv.p, al, znl, V.delta.p, q, nl, first, s);
-    const T* dfin = schur_steps<T>(D.S.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, first ? nullptr : zl, al,
-                                   znl, ks, nl, D.sg_S, s);
+    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, sdv, al, znl, V.delta.p, q, nl, first, s);
+    const T* dfin = schur(D.S, first ? nullptr : zl, false);
     if (uzawa)
       uzawa_update<T>(first ? nullptr : zu, wa, al, znu, nu, s);
     else
@@ -532,10 +544,9 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
       else
         tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, false, D.sg_K, s);
     }
-    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, su, uzawa ? nullptr : V.ainv.p, V.sdinv.p, al, znl,
+    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), zu, zl, bl, su, uzawa ? nullptr : V.ainv.p, sdv, al, znl,
                  V.delta.p, q, nl, first, s);
-    const T* dfin = schur_steps<T>(D.ST.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, first ? nullptr : zl, al,
-                                   znl, ks, nl, D.sg_S, s);
+    const T* dfin = schur(D.ST, first ? nullptr : zl, true);
     tcorrect_u<T>(D.BT.view<T>(), su, dfin, V.jinv.p, om, uzawa ? T(1) : al, zu, znu, keep_w ? V.aux1.p : nullptr,
                   keep_w ? V.aux2.p : nullptr, nu, first, s);
     T* wa = V.aux2.p;
@@ -951,7 +962,7 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
       (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 1 ||
       o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
-      o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 1 || o.schur_sweeps < 1 ||
+      o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 2 || o.schur_sweeps < 1 ||
       o.schur_sweeps > 64 || !(o.sa_omega > 0.0) || !std::isfinite(o.sa_omega) || o.coarse_solver < 0 ||
       o.coarse_solver > 1 || o.coarse_sweeps < 1 || o.coarse_sweeps > 64 || o.smoother < 0 || o.smoother > 2 ||
       !(o.simple_alpha > 0.0) || !std::isfinite(o.simple_alpha))
@@ -1112,10 +1123,22 @@ int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_
 int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols, int64_t* nnz,
                          int64_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> int {
-    if (!h || level < 0 || level >= (int)h->host.size() || which < 0 || which > 6)
+    if (!h || level < 0 || level >= (int)h->host.size() || which < 0 || which > 7)
       api_fail(CAMG_ERR_INVALID_ARG, "level/which");
     const HostLevel& L = h->host[level];
-    const HostCSR* M[7] = {&L.K, &L.G, &L.B, &L.C, &L.P_u, &L.P_l, &L.S};
+    HostCSR blk;  // which = 7: the inverse nodal Schur blocks as a block-diagonal matrix
+    if (which == 7 && !L.sblk_inv.empty()) {
+      const int bs = L.bs_l;
+      const int64_t nl = L.n_l();
+      blk.nrows = blk.ncols = nl;
+      blk.rp.resize((size_t)nl + 1);
+      for (int64_t j = 0; j <= nl; ++j) blk.rp[(size_t)j] = j * bs;
+      blk.ci.resize((size_t)(nl * bs));
+      for (int64_t j = 0; j < nl; ++j)
+        for (int c = 0; c < bs; ++c) blk.ci[(size_t)(j * bs + c)] = (int32_t)((j / bs) * bs + c);
+      blk.v = L.sblk_inv;
+    }
+    const HostCSR* M[8] = {&L.K, &L.G, &L.B, &L.C, &L.P_u, &L.P_l, &L.S, &blk};
     if ((which == 4 || which == 5) && level + 1 >= (int)h->host.size())
       api_fail(CAMG_ERR_INVALID_ARG, "no transfer on coarsest");
     const HostCSR& A = *M[which];

@@ -171,7 +171,7 @@ def test_robust_options_validated():
     from paper_1912_09056_amd.camg import AMGOptions, AMGSolver, CamgError
 
     p = make_workload("contact2d_16")
-    for bad in (dict(schur_sweeps=0), dict(schur_sweeps=65), dict(schur=2), dict(prolongator=2),
+    for bad in (dict(schur_sweeps=0), dict(schur_sweeps=65), dict(schur=3), dict(prolongator=2),
                 dict(sa_omega=0.0), dict(sa_omega=float("nan"))):
         with pytest.raises(CamgError) as e:
             AMGSolver.from_problem(p, AMGOptions(max_levels=2, **bad), host_only=True)
@@ -217,3 +217,36 @@ def test_host_hierarchy_standard_basis_matches_oracle(kappa, levels):
         if l + 1 < len(ora):
             du, dl = lib.aggregates(l)
             assert np.array_equal(du, L.agg_u) and np.array_equal(dl, L.agg_l), l
+
+
+@pytest.mark.parametrize("smoother", [0, 2])
+def test_host_block_schur_matches_oracle(smoother):
+    # rotated clamped two-body problem: the kept Schur matrix and the inverse
+    # nodal blocks (of S_a for Braess-Sarazin) on every smoothing level
+    import scipy.sparse as sp
+
+    from contactgen import rotate_problem
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
+
+    p = make_contact_problem(3, (4, 4, 3), (5, 5, 3), slave_box=((0.1, 0.1, 0.0), (0.8, 0.8, 0.5)),
+                             master_box=((0.0, 0.0, -1.0), (1.0, 1.0, 1.0)), top_bc="clamped", rhs="gap",
+                             penetration=0.01)
+    prob = rotate_problem(p, np.pi / 8, 3 * np.pi / 8)
+    names = {0: "simple", 2: "braess_sarazin"}
+    ora = build_hierarchy(prob, OracleOptions(max_levels=3, max_coarse_rows=50, schur="block", schur_sweeps=2,
+                                              smoother=names[smoother], simple_alpha=1.9))
+    lib = AMGSolver.from_problem(prob, AMGOptions(max_levels=3, max_coarse_rows=50, schur=2, schur_sweeps=2,
+                                                  smoother=smoother, simple_alpha=1.9), host_only=True)
+    assert lib.n_levels == len(ora) == 3
+    for l, L in enumerate(ora[:-1]):
+        key = "bs_sb_inv" if smoother == 2 else "sb_inv"
+        S_ref = L.extra["bs_S"] if smoother == 2 else L.S
+        S = lib.level_matrix(l, "S")
+        assert np.array_equal(S.indptr, S_ref.indptr) and np.array_equal(S.indices, S_ref.indices), l
+        assert np.abs(S.data - S_ref.data).max() <= 1e-13 * np.abs(S_ref.data).max(), l
+        Bi = lib.level_matrix(l, "Sblk_inv").toarray()
+        ref = sp.block_diag(list(L.extra[key])).toarray()
+        assert np.abs(Bi - ref).max() <= 1e-11 * np.abs(ref).max(), l
+    # the diagonal options keep no blocks
+    lib0 = AMGSolver.from_problem(prob, AMGOptions(max_levels=2, max_coarse_rows=50, schur=1), host_only=True)
+    assert lib0.level_matrix(0, "Sblk_inv").shape == (0, 0)
