@@ -63,7 +63,7 @@ class AMGOptions:
     jacobi_sweeps: int = 1
     jacobi_omega: float = 0.8
     simple_alpha: float = 0.8
-    atilde: str = "rowsum_abs"  # or "diag"
+    atilde: str = "rowsum_abs"  # or "diag", or "nodal" (block lumping per node, see nodal_lumping)
     jacobi_diag: str = "atilde"  # relaxation diagonal of the prediction: "atilde" or "diag"
     prolongator: str = "pa"  # displacement transfers: "pa" tentative, "sa" smoothed
     sa_omega: float = 4.0 / 3.0  # prolongator smoothing factor (with the lumped diagonal)
@@ -304,10 +304,52 @@ def galerkin(R, A, P):
     return _on_pattern(R @ A @ P, _pattern(R) @ _pattern(A) @ _pattern(P))
 
 
-def smoothed_prolongator(K, P_hat, omega):
+def nodal_lumping(K, bs):
+    """Nodal SIMPLEC lumping: for every node i (bs consecutive dofs) the
+    bs x bs block K_ii plus (sum over nodes j != i of ||K_ij||_F) times the
+    identity.  For symmetric K, 2|x_i^T K_ij x_j| <= ||K_ij|| (|x_i|^2 +
+    |x_j|^2) gives x^T K x <= x^T Atilde x, the block analogue of the row-sum
+    bound, and a rotation of the node's frame (K_ij -> R K_ij R^T) maps the
+    blocks to R Atilde_i R^T since the Frobenius norm is invariant.
+    Returns the blocks, shape (n / bs, bs, bs)."""
+    n = K.shape[0]
+    if bs <= 0 or n % bs:
+        raise ValueError("dof count is not a multiple of the node block size")
+    nb = n // bs
+    coo = K.tocoo()
+    rn, cn = coo.row // bs, coo.col // bs
+    A = np.zeros((nb, bs, bs))
+    d = rn == cn
+    np.add.at(A, (rn[d], coo.row[d] % bs, coo.col[d] % bs), coo.data[d])
+    key = rn[~d].astype(np.int64) * nb + cn[~d]
+    uk, inv = np.unique(key, return_inverse=True)
+    fro = np.sqrt(np.bincount(inv, weights=coo.data[~d] ** 2, minlength=len(uk)))
+    off = np.zeros(nb)
+    np.add.at(off, uk // nb, fro)
+    return A + off[:, None, None] * np.eye(bs)[None, :, :]
+
+
+def block_diag_matrix(blocks):
+    """The block-diagonal CSR matrix of a (nb, bs, bs) stack."""
+    nb, bs, _ = blocks.shape
+    rows = np.repeat(np.arange(nb * bs), bs)
+    cols = (np.arange(nb)[:, None, None] * bs + np.zeros((1, bs, 1), int) + np.arange(bs)[None, None, :]).ravel()
+    return sp.csr_matrix((blocks.reshape(-1), (rows, cols)), shape=(nb * bs, nb * bs))
+
+
+def smoothed_prolongator(K, P_hat, omega, Ainv_blocks=None):
     """P = P_hat - omega Atilde^-1 K P_hat (Sec. 3.1.2, prolongator smoothing)
     with the lumped diagonal Atilde = diag(sum_j |K_ij|), on the symbolic
-    pattern of P_hat plus that of K P_hat."""
+    pattern of P_hat plus that of K P_hat.  With Ainv_blocks (the inverse
+    nodal lumping blocks) Atilde^-1 is that block-diagonal matrix, on the
+    pattern of P_hat plus that of Atilde^-1 K P_hat."""
+    if Ainv_blocks is not None:
+        D = block_diag_matrix(Ainv_blocks)
+        DKP = _on_pattern(D @ (K @ P_hat), _pattern(D) @ _pattern(K) @ _pattern(P_hat) + _pattern(P_hat))
+        Ph = _on_pattern(P_hat, DKP)
+        out = DKP.copy()
+        out.data = Ph.data - omega * DKP.data
+        return out
     w = omega / np.asarray(abs(K).sum(axis=1)).ravel()
     KP = _on_pattern(K @ P_hat, _pattern(K) @ _pattern(P_hat) + _pattern(P_hat))
     Ph = _on_pattern(P_hat, KP)
@@ -318,7 +360,12 @@ def smoothed_prolongator(K, P_hat, omega):
 
 
 def schur_matrix(L: "Level", At_inv):
-    """B Atilde^-1 G - C on the symbolic pattern of B G plus that of C."""
+    """B Atilde^-1 G - C on the symbolic pattern of B G plus that of C (of
+    B Atilde^-1 G plus C's for nodal lumping blocks, At_inv of shape
+    (nb, bs, bs))."""
+    if np.ndim(At_inv) == 3:
+        D = block_diag_matrix(At_inv)
+        return _on_pattern(L.B @ D @ L.G - L.C, _pattern(L.B) @ _pattern(D) @ _pattern(L.G) + _pattern(L.C))
     BA = L.B @ sp.diags(At_inv)
     return _on_pattern(BA @ L.G - L.C, _pattern(L.B) @ _pattern(L.G) + _pattern(L.C))
 
@@ -356,6 +403,8 @@ def smoother_data(L: Level, opts: AMGOptions):
     dK = L.K.diagonal()
     if np.any(dK == 0.0):
         raise ZeroDivisionError("zero diagonal in K")
+    if opts.atilde == "nodal":
+        return _smoother_data_nodal(L, opts)
     if opts.atilde == "rowsum_abs":
         At = np.asarray(abs(L.K).sum(axis=1)).ravel()
     else:
@@ -404,6 +453,46 @@ def smoother_data(L: Level, opts: AMGOptions):
         L.extra["bs_sd_inv"] = 1.0 / da
         if opts.schur_sweeps > 1:
             L.extra["bs_S"] = Sa
+
+
+def _smoother_data_nodal(L: Level, opts: AMGOptions):
+    """Smoother data with the nodal lumping (atilde="nodal"): the inverse
+    blocks serve as Atilde^-1 in the back-substitution, the Schur matrix and
+    (jacobi_diag="atilde" only) as the block relaxation of the prediction;
+    Schur relaxation as for the point lumping, from S = B Atilde^-1 G - C."""
+    if opts.jacobi_diag != "atilde":
+        raise ValueError("the nodal lumping relaxes the prediction with its own blocks")
+    blocks = nodal_lumping(L.K, L.bs_u)
+    try:
+        At_inv = np.linalg.inv(blocks)
+    except np.linalg.LinAlgError:
+        raise ZeroDivisionError("singular nodal lumping block") from None
+    L.dinv = At_inv
+    L.atilde_inv = At_inv
+    L.extra.pop("sb_inv", None)
+    L.extra.pop("bs_sb_inv", None)
+    Sa_inv = At_inv / opts.simple_alpha if opts.smoother == "braess_sarazin" else At_inv
+    S = schur_matrix(L, Sa_inv)
+    key_blk, key_d = ("bs_sb_inv", "bs_sd_inv") if opts.smoother == "braess_sarazin" else ("sb_inv", None)
+    if opts.schur == "block":
+        L.extra[key_blk] = node_block_inverse(S, L.bs_l, L.lm_node)
+        Sd = None
+    elif opts.schur == "l1":
+        Sd = np.sign(S.diagonal()) * np.asarray(abs(S).sum(axis=1)).ravel()
+    else:
+        Sd = S.diagonal()
+    if Sd is not None and np.any(Sd == 0.0):
+        raise ZeroDivisionError("zero Schur diagonal")
+    if opts.smoother == "braess_sarazin":
+        L.sd_inv = None
+        if Sd is not None:
+            L.extra[key_d] = 1.0 / Sd
+        if opts.schur_sweeps > 1:
+            L.extra["bs_S"] = S
+        L.S = None
+    else:
+        L.sd_inv = None if Sd is None else 1.0 / Sd
+        L.S = S if opts.schur_sweeps > 1 else None
 
 
 def node_block_inverse(S, bs, lm_node=None):
@@ -494,7 +583,10 @@ def coarsen(L: Level, opts: AMGOptions = None):
     P_u, ns_u_c = tentative_prolongator(agg_u, n_agg_u, node_of_dof_u, L.nullspace_u, dirichlet)
     P_l, ns_l_c = tentative_prolongator(agg_l, n_agg_l, L.lm_node, L.nullspace_l, np.zeros(L.n_l, bool))
     if opts.prolongator == "sa":
-        P_u = smoothed_prolongator(L.K, P_u, opts.sa_omega)
+        if opts.atilde == "nodal":
+            P_u = smoothed_prolongator(L.K, P_u, opts.sa_omega, np.linalg.inv(nodal_lumping(L.K, L.bs_u)))
+        else:
+            P_u = smoothed_prolongator(L.K, P_u, opts.sa_omega)
     R_u = P_u.T.tocsr()
     R_l = P_l.T.tocsr()
     L.agg_u, L.agg_l, L.dmap, L.P_u, L.P_l = agg_u, agg_l, dmap, P_u, P_l

@@ -46,23 +46,34 @@ from __future__ import annotations
 import numpy as np
 
 
-def jacobi(K, dinv, r, omega, sweeps):
-    """sweeps damped-Jacobi steps on K w = r from w = 0."""
+def jacobi(K, dinv, r, omega, sweeps, transpose=False):
+    """sweeps damped-Jacobi steps on K w = r from w = 0; dinv is the inverse
+    relaxation diagonal, or a (nb, bs, bs) stack of inverse nodal blocks
+    (block Jacobi; applied transposed with transpose, for K^T)."""
     w = np.zeros_like(r)
     for _ in range(sweeps):
-        w = w + omega * dinv * (r - K @ w)
+        if np.ndim(dinv) == 1:
+            w = w + omega * dinv * (r - K @ w)
+        else:
+            w = w + omega * node_block_solve(dinv, r - K @ w, transpose)
     return w
+
+
+def lumped(L, v, scale=1.0, transpose=False):
+    """scale * Atilde^-1 v with the level's lumping: the diagonal, or the
+    nodal blocks (transposed with transpose)."""
+    if np.ndim(L.atilde_inv) == 1:
+        return scale * L.atilde_inv * v
+    return scale * node_block_solve(L.atilde_inv, v, transpose)
 
 
 def node_block_solve(blk_inv, r, transpose=False):
     """Per multiplier node j (bs consecutive dofs): blk_inv[j] @ r_j, or
     blk_inv[j]^T @ r_j with transpose (the inverse of the transposed block)."""
     nb, bs, _ = blk_inv.shape
-    out = np.empty(nb * bs)
-    for j in range(nb):
-        Mj = blk_inv[j].T if transpose else blk_inv[j]
-        out[j * bs:(j + 1) * bs] = Mj @ r[j * bs:(j + 1) * bs]
-    return out
+    R = np.asarray(r).reshape(nb, bs)
+    # out_j[a] = sum_b M_j[a, b] r_j[b]   (M_j[b, a] with transpose)
+    return np.einsum("nba,nb->na" if transpose else "nab,nb->na", blk_inv, R).reshape(-1)
 
 
 def _schur_relax(S_of, d_inv, blk_inv, rt, sweeps, transpose):
@@ -111,7 +122,7 @@ def cheap_simple_sweep(L, b, z, omega, alpha, jac_sweeps=1, predict=None, schur_
     delta = -schur_apply(L, rt, schur_sweeps) if schur_solve is None else -schur_solve(rt)
     out = np.empty_like(z)
     out[n_u:] = zl + alpha * delta
-    out[:n_u] = zu + w - alpha * L.atilde_inv * (L.G @ delta)
+    out[:n_u] = zu + w - lumped(L, L.G @ delta, alpha)
     return out
 
 
@@ -147,7 +158,7 @@ def cheap_uzawa_sweep_adjoint(L, b, z, omega, alpha, jac_sweeps=1, KT=None, schu
     delta = -schur_apply(L, sl, schur_sweeps, transpose=True)
     out = np.empty_like(z)
     out[n_u:] = zl + alpha * delta
-    out[:n_u] = zu + alpha * jacobi(KT, L.dinv, su - L.B.T @ delta, omega, jac_sweeps)
+    out[:n_u] = zu + alpha * jacobi(KT, L.dinv, su - L.B.T @ delta, omega, jac_sweeps, transpose=True)
     return out
 
 
@@ -162,12 +173,12 @@ def braess_sarazin_sweep(L, b, z, alpha, schur_sweeps=1, schur_solve=None):
     n_u = L.n_u
     zu, zl = z[:n_u], z[n_u:]
     ru = b[:n_u] - (L.K @ zu + L.G @ zl)
-    u_half = zu + L.atilde_inv * ru / alpha
+    u_half = zu + lumped(L, ru) / alpha
     rt = b[n_u:] - (L.B @ u_half + L.C @ zl)
     delta = -_bs_schur(L, rt, schur_sweeps, False) if schur_solve is None else -schur_solve(rt)
     out = np.empty_like(z)
     out[n_u:] = zl + delta
-    out[:n_u] = u_half - L.atilde_inv * (L.G @ delta) / alpha
+    out[:n_u] = u_half - lumped(L, L.G @ delta) / alpha
     return out
 
 
@@ -180,10 +191,10 @@ def braess_sarazin_sweep_adjoint(L, b, z, alpha, schur_sweeps=1, KT=None):
     zu, zl = z[:n_u], z[n_u:]
     su = b[:n_u] - (KT @ zu + L.B.T @ zl)
     sl = b[n_u:] - (L.G.T @ zu + L.C.T @ zl)
-    delta = -_bs_schur(L, sl - L.G.T @ (L.atilde_inv * su) / alpha, schur_sweeps, True)
+    delta = -_bs_schur(L, sl - L.G.T @ lumped(L, su, transpose=True) / alpha, schur_sweeps, True)
     out = np.empty_like(z)
     out[n_u:] = zl + delta
-    out[:n_u] = zu + L.atilde_inv * (su - L.B.T @ delta) / alpha
+    out[:n_u] = zu + lumped(L, su - L.B.T @ delta, transpose=True) / alpha
     return out
 
 
@@ -204,8 +215,8 @@ def cheap_simple_sweep_adjoint(L, b, z, omega, alpha, jac_sweeps=1, KT=None, sch
     zu, zl = z[:n_u], z[n_u:]
     su = b[:n_u] - (KT @ zu + L.B.T @ zl)
     sl = b[n_u:] - (L.G.T @ zu + L.C.T @ zl)
-    delta = -schur_apply(L, sl - L.G.T @ (L.atilde_inv * su), schur_sweeps, transpose=True)
+    delta = -schur_apply(L, sl - L.G.T @ lumped(L, su, transpose=True), schur_sweeps, transpose=True)
     out = np.empty_like(z)
     out[n_u:] = zl + alpha * delta
-    out[:n_u] = zu + jacobi(KT, L.dinv, su - alpha * (L.B.T @ delta), omega, jac_sweeps)
+    out[:n_u] = zu + jacobi(KT, L.dinv, su - alpha * (L.B.T @ delta), omega, jac_sweeps, transpose=True)
     return out

@@ -125,3 +125,97 @@ def test_block_schur_keeps_cheap_simple_iterations_under_rotation():
     for ang in [(np.pi / 4, np.pi / 8), (3 * np.pi / 8, np.pi / 4)]:
         assert its["block", ang] <= 1.25 * base, its
         assert its["diag", ang] > 2 * base, its
+
+
+# ---- nodal lumping --------------------------------------------------------------
+
+
+def test_nodal_lumping_is_the_block_plus_frobenius_sums():
+    from oracle.hierarchy import nodal_lumping
+
+    p = rotate_problem(_clamped(), np.pi / 8, np.pi / 4)
+    Kd = p.K.toarray()
+    got = nodal_lumping(p.K, 3)
+    for i in range(p.n_u // 3):
+        bi = slice(3 * i, 3 * i + 3)
+        off = sum(np.sqrt((Kd[bi, 3 * j:3 * j + 3] ** 2).sum()) for j in range(p.n_u // 3) if j != i)
+        assert np.allclose(got[i], Kd[bi, bi] + off * np.eye(3), rtol=0, atol=1e-14 * np.abs(Kd).max())
+
+
+def test_nodal_lumping_bounds_the_spectrum():
+    """x^T K x <= x^T Atilde x: the eigenvalues of Atilde^-1 K lie in (0, 1]."""
+    from oracle.hierarchy import block_diag_matrix, nodal_lumping
+
+    p = rotate_problem(_clamped(), np.pi / 3, np.pi / 5)
+    A = block_diag_matrix(nodal_lumping(p.K, 3)).toarray()
+    ev = np.linalg.eigvals(np.linalg.solve(A, p.K.toarray())).real
+    assert ev.min() > 0 and ev.max() <= 1 + 1e-12, (ev.min(), ev.max())
+
+
+NODAL = dict(max_levels=3, max_coarse_rows=50, atilde="nodal", schur="block", nu_pre=3, nu_post=3)
+
+
+@pytest.mark.parametrize("smoother", ["simple", "uzawa", "braess_sarazin"])
+@pytest.mark.parametrize("prolongator", ["pa", "sa"])
+def test_nodal_options_are_rotation_covariant(smoother, prolongator):
+    """With the nodal lumping and the nodal Schur blocks every ingredient
+    transforms with the rotation at any angle, so the V-cycle of the rotated
+    problem is the rotated V-cycle: M'(Q r) = Q M r (the coarse levels are the
+    same matrices, the fine-level blocks are R X R^T)."""
+    p = _clamped()
+    angles = (0.3, 1.1)
+    q = rotate_problem(p, *angles)
+    R = _R(*angles)
+    opts = AMGOptions(**NODAL, smoother=smoother, prolongator=prolongator, simple_alpha=0.7, schur_sweeps=2)
+    r = np.random.default_rng(6).standard_normal(p.n)
+    z = vcycle(build_hierarchy(p, opts), r, opts)
+    rq = np.concatenate([_rot(r[:p.n_u], R), r[p.n_u:]])
+    lq = build_hierarchy(q, opts)
+    zq = vcycle(lq, rq, opts)
+    expect = np.concatenate([_rot(z[:p.n_u], R), _rot(z[p.n_u:], R)])
+    assert np.linalg.norm(zq - expect) <= 1e-10 * np.linalg.norm(expect)
+    # the point lumping is not covariant
+    popts = AMGOptions(**dict(NODAL, atilde="rowsum_abs"), smoother=smoother, prolongator=prolongator,
+                       simple_alpha=0.7, schur_sweeps=2)
+    zp = vcycle(build_hierarchy(p, popts), r, popts)
+    zpq = vcycle(build_hierarchy(q, popts), rq, popts)
+    ep = np.concatenate([_rot(zp[:p.n_u], R), _rot(zp[p.n_u:], R)])
+    assert np.linalg.norm(zpq - ep) > 1e-6 * np.linalg.norm(ep)
+
+
+@pytest.mark.parametrize("smoother", ["simple", "uzawa", "braess_sarazin"])
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_nodal_vcycle_transpose_with_nonsymmetric_K(smoother, sweeps):
+    """A nonsymmetric perturbation of K makes the lumping blocks
+    nonsymmetric, so the adjoint sweep must apply them transposed."""
+    import dataclasses
+
+    p = rotate_problem(_clamped(), 0.4, 0.9)
+    K = p.K.tocoo()
+    rng = np.random.default_rng(7)
+    free = ~p.dirichlet[K.row] & ~p.dirichlet[K.col]
+    data = K.data + np.where(free, 0.05 * np.abs(K.data).max() * rng.uniform(-1, 1, K.nnz), 0.0)
+    import scipy.sparse as sp
+
+    p2 = dataclasses.replace(p, K=sp.csr_matrix((data, (K.row, K.col)), shape=K.shape))
+    opts = AMGOptions(**NODAL, smoother=smoother, simple_alpha=0.7, schur_sweeps=sweeps, jacobi_sweeps=2)
+    lv = build_hierarchy(p2, opts)
+    assert np.abs(lv[0].atilde_inv - lv[0].atilde_inv.transpose(0, 2, 1)).max() > 1e-8
+    u, v = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    a1 = v @ vcycle(lv, u, opts)
+    a2 = vcycle(lv, v, opts, transpose=True) @ u
+    assert abs(a1 - a2) <= 1e-11 * abs(a1)
+
+
+@pytest.mark.parametrize("smoother", ["simple", "uzawa", "braess_sarazin"])
+def test_nodal_iterations_do_not_depend_on_the_angles(smoother):
+    p = _clamped((6, 6, 4), (7, 7, 4))
+    opts = AMGOptions(**NODAL, smoother=smoother, simple_alpha=1.9 if smoother == "braess_sarazin" else 0.7,
+                      jacobi_omega=0.7)
+    its = []
+    for ang in [(0.0, 0.0), (np.pi / 8, np.pi / 4), (3 * np.pi / 8, np.pi / 8), (np.pi / 2, 3 * np.pi / 8)]:
+        q = rotate_problem(p, *ang)
+        r = solve(build_hierarchy(q, opts), opts, q.b, rtol=1e-8, max_iters=300)
+        assert r.converged
+        its.append(r.iters)
+    assert max(its) - min(its) <= 1, its
