@@ -547,11 +547,18 @@ def rotate_problem(p: ContactProblem, angle_y: float, angle_z: float) -> Contact
         M.sort_indices()
         return M
 
+    # a clamped node's rows and columns of K are identity ones, and R R^T = I
+    # keeps them so; write them exactly rather than with rounding residue
+    K = sp.csr_matrix(Q @ p.K @ Q.T).tocoo()
+    keep = ~(p.dirichlet[K.row] | p.dirichlet[K.col])
+    n_dir = np.nonzero(p.dirichlet)[0]
+    K = sp.csr_matrix((np.concatenate([K.data[keep], p.K.diagonal()[n_dir]]),
+                       (np.concatenate([K.row[keep], n_dir]), np.concatenate([K.col[keep], n_dir]))), shape=K.shape)
     b = p.b.copy()
     b[: p.n_u] = Q @ p.b[: p.n_u]
     return ContactProblem(
         dim=d,
-        K=clean(Q @ p.K @ Q.T),
+        K=clean(K),
         G=clean(Q @ p.G @ Ql.T),
         B=clean(p.B @ Q.T),
         C=clean(p.C @ Ql.T),
