@@ -88,6 +88,7 @@ typedef struct {
 /* Preconditioner options (defaults from amg_default_options). */
 #define CAMG_ATILDE_ROWSUM_ABS 0 /* SIMPLEC lumping diag(sum_j |K_ij|)     */
 #define CAMG_ATILDE_DIAG 1       /* diag(K)                                 */
+#define CAMG_ATILDE_NODAL 2      /* nodal blocks K_ii + sum_j ||K_ij||_F I   */
 #define CAMG_JACOBI_ATILDE 0     /* Jacobi prediction relaxes with Atilde   */
 #define CAMG_JACOBI_DIAG 1       /* Jacobi prediction relaxes with diag(K)  */
 #define CAMG_PREC_FP64 0         /* hierarchy, smoother, transfers in FP64  */
@@ -110,7 +111,7 @@ typedef struct {
   int32_t max_coarse_rows; /* stop coarsening at or below this many rows   */
   int32_t nu_pre, nu_post; /* CheapSIMPLE sweeps before / after correction */
   int32_t jacobi_sweeps;   /* damped Jacobi sweeps in the prediction (>=1) */
-  int32_t atilde;          /* CAMG_ATILDE_*                                */
+  int32_t atilde;          /* CAMG_ATILDE_* (NODAL needs jacobi_diag = CAMG_JACOBI_ATILDE) */
   int32_t jacobi_diag;     /* CAMG_JACOBI_*                                */
   int32_t precision;       /* CAMG_PREC_*                                  */
   int32_t spmv_format;     /* CAMG_SPMV_* (storage of K on device)         */
@@ -133,7 +134,17 @@ typedef struct {
    *   multipliers the normal and tangential constraint rows of a node mix its
    *   components wherever the interface normal is not a coordinate axis, and
    *   the diagonal alone can vanish there (the rotated two-body experiment of
-   *   Sec. 6.1).  A singular node block is CAMG_ERR_ZERO_DIAG. */
+   *   Sec. 6.1).  A singular node block is CAMG_ERR_ZERO_DIAG.
+   * CAMG_ATILDE_NODAL replaces the point lumping by one block per node (bs_u
+   *   dofs): A_i = K_ii + (sum over other nodes j of ||K_ij||_F) I, which
+   *   bounds x^T K x from above for symmetric K as the row sums do, and
+   *   transforms as R A_i R^T when the node frames rotate.  Its inverse
+   *   blocks relax the prediction (block Jacobi), back-substitute and form
+   *   S = B A^-1 G - C (and smooth the prolongator with CAMG_PROLONG_SMOOTHED);
+   *   with CAMG_SCHUR_BLOCK every smoother is then covariant under a rigid
+   *   rotation of the problem (the iteration counts do not depend on the
+   *   angles).  The nodal sweep runs from generic kernels (block applies and
+   *   separate products) rather than the fused point-diagonal ones. */
   int32_t prolongator;     /* CAMG_PROLONG_*                               */
   int32_t schur;           /* CAMG_SCHUR_*                                 */
   int32_t schur_sweeps;    /* 1..64                                        */
@@ -214,7 +225,7 @@ int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_
 /* Copies block `which` (0=K, 1=G, 2=B, 3=C, 4=P_u, 5=P_l, 6=S, the Schur
  * matrix B Atilde^-1 G - C kept when schur_sweeps > 1, else 0 x 0; 7=the
  * inverse nodal blocks of S as a block-diagonal matrix with CAMG_SCHUR_BLOCK,
- * else 0 x 0) of
+ * 8=the inverse nodal lumping blocks with CAMG_ATILDE_NODAL, else 0 x 0) of
  * `level` to host arrays in FP64 (rowptr: nrows+1, col/val: nnz).  Call with
  * NULL arrays to query *nrows, *ncols, *nnz first. */
 int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols,

@@ -195,7 +195,7 @@ class AMGOptions:
     nu_pre: int = 2
     nu_post: int = 2
     jacobi_sweeps: int = 1
-    atilde: int = 0
+    atilde: int = 0  # SIMPLEC lumping: 0 row sums of |K|, 1 diag(K), 2 nodal blocks (rotation-covariant)
     jacobi_diag: int = 0
     precision: int = PREC_FP64
     spmv_format: int = 0  # 0 auto, 1 CSR, 2 sliced blocked-ELL
@@ -325,13 +325,14 @@ class AMGSolver:
         return du, dl
 
     def level_matrix(self, level: int, which: str):
-        """Host copy of block K/G/B/C/P_u/P_l/S/Sblk_inv of a level as scipy
-        CSR (S: the Schur matrix, kept only with schur_sweeps > 1; Sblk_inv:
-        the inverse nodal blocks of S with the block Schur option; else
+        """Host copy of block K/G/B/C/P_u/P_l/S/Sblk_inv/Ablk_inv of a level as
+        scipy CSR (S: the Schur matrix, kept only with schur_sweeps > 1;
+        Sblk_inv: the inverse nodal blocks of S with the block Schur option;
+        Ablk_inv: the inverse nodal lumping blocks with atilde=2; else
         0 x 0)."""
         import scipy.sparse as sp
 
-        w = {"K": 0, "G": 1, "B": 2, "C": 3, "P_u": 4, "P_l": 5, "S": 6, "Sblk_inv": 7}[which]
+        w = {"K": 0, "G": 1, "B": 2, "C": 3, "P_u": 4, "P_l": 5, "S": 6, "Sblk_inv": 7, "Ablk_inv": 8}[which]
         nr, nc, nz = c_int64(), c_int64(), c_int64()
         _check(self.lib.amg_get_level_matrix(self.handle, level, w, byref(nr), byref(nc), byref(nz), None, None, None))
         rp = np.zeros(nr.value + 1, np.int64)

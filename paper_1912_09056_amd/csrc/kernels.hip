@@ -426,6 +426,46 @@ __global__ void __launch_bounds__(kBlock) k_schur_block(DCSR<T> S, const T* __re
   }
 }
 
+// Nodal lumping option, one thread per node j (BS consecutive dofs):
+//   v_j = scale * M_j x_j   (M_j^T x_j with TRANS; M row-major per node),
+//   w_out_j = v_j, y_out_j = y_in_j + v_j (y_in null: zero).
+// y_in may alias y_out (each thread reads its own rows first).
+template <typename T, int BS, bool TRANS>
+__global__ void __launch_bounds__(kBlock) k_node_apply(const T* __restrict__ M, const T* __restrict__ x, T scale,
+                                                       const T* y_in, T* y_out, T* __restrict__ w_out, int n_nodes) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n_nodes) return;
+  const T* Mj = M + (size_t)j * (BS * BS);
+  T xv[BS], v[BS];
+#pragma unroll
+  for (int b = 0; b < BS; ++b) xv[b] = x[(size_t)j * BS + b];
+#pragma unroll
+  for (int a = 0; a < BS; ++a) {
+    T acc = T(0);
+#pragma unroll
+    for (int b = 0; b < BS; ++b) acc += (TRANS ? Mj[b * BS + a] : Mj[a * BS + b]) * xv[b];
+    v[a] = scale * acc;
+  }
+#pragma unroll
+  for (int a = 0; a < BS; ++a) {
+    const size_t row = (size_t)j * BS + a;
+    if (w_out) w_out[row] = v[a];
+    if (y_out) y_out[row] = (y_in ? y_in[row] : T(0)) + v[a];
+  }
+}
+
+// y = b - a * (A x)   (b null: zero).
+template <typename T, int SG>
+__global__ void __launch_bounds__(kBlock) k_spmv_axpy(DCSR<T> A, const T* __restrict__ x, T a,
+                                                      const T* __restrict__ b, T* __restrict__ y, int n) {
+  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (row >= n) return;
+  T s = A.nnz ? row_dot<T, SG>(A, x, row, lane) : T(0);
+  s = sg_reduce<T, SG>(s);
+  if (lane == 0) y[row] = (b ? b[row] : T(0)) - a * s;
+}
+
 template <typename T, int SG>
 __global__ void __launch_bounds__(kBlock) k_smooth_u_first_corr(DCSR<T> G, const T* __restrict__ bu,
                                                                 const T* __restrict__ jinv, T omega,
@@ -1036,6 +1076,39 @@ T* schur_block_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* blk,
 }
 
 template <typename T>
+void node_apply(const T* M, const T* x, T scale, const T* y_in, T* y_out, T* w_out, int n, int bs, bool trans,
+                hipStream_t s) {
+  if (n <= 0) return;
+  if (bs < 1 || bs > 6 || n % bs) throw std::runtime_error("node_apply: node block size must be 1..6 and divide n");
+  const int nn = n / bs;
+  const unsigned g = grid_for(nn, kBlock);
+#define CAMG_NODE_APPLY_LAUNCH(BSV)                                                                     \
+  if (trans)                                                                                            \
+    k_node_apply<T, BSV, true><<<g, kBlock, 0, s>>>(M, x, scale, y_in, y_out, w_out, nn);                \
+  else                                                                                                  \
+    k_node_apply<T, BSV, false><<<g, kBlock, 0, s>>>(M, x, scale, y_in, y_out, w_out, nn);
+  switch (bs) {
+    case 1: CAMG_NODE_APPLY_LAUNCH(1) break;
+    case 2: CAMG_NODE_APPLY_LAUNCH(2) break;
+    case 3: CAMG_NODE_APPLY_LAUNCH(3) break;
+    case 4: CAMG_NODE_APPLY_LAUNCH(4) break;
+    case 5: CAMG_NODE_APPLY_LAUNCH(5) break;
+    default: CAMG_NODE_APPLY_LAUNCH(6) break;
+  }
+#undef CAMG_NODE_APPLY_LAUNCH
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void spmv_axpy(const DCSR<T>& A, const T* x, T a, const T* b, T* y, int n, hipStream_t s) {
+  if (n <= 0) return;
+  CAMG_SG_DISPATCH(rows_sg(A.nnz, n), {
+    k_spmv_axpy<T, SG><<<grid_for(n, kBlock / SG), kBlock, 0, s>>>(A, x, a, b, y, n);
+  });
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
 void correct_u(const DCSR<T>& G, const int32_t* rows, int n_rows, const T* delta, const T* ainv, T alpha, T* znu,
                hipStream_t s) {
   if (n_rows <= 0) return;
@@ -1385,6 +1458,8 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
                              hipStream_t);                                                                         \
   template T* schur_block_steps<T>(const DCSR<T>&, const T*, T*, T*, const T*, bool, const T*, T, T*, int, int, int, \
                                    hipStream_t);                                                                   \
+  template void node_apply<T>(const T*, const T*, T, const T*, T*, T*, int, int, bool, hipStream_t);               \
+  template void spmv_axpy<T>(const DCSR<T>&, const T*, T, const T*, T*, int, hipStream_t);                        \
   template void correct_u<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, hipStream_t);         \
   template void tsmooth_u<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, T*, int, bool, int,      \
                              hipStream_t);                                                                         \

@@ -68,6 +68,18 @@ template <typename T>
 T* schur_block_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* blk, bool trans, const T* zl, T alpha,
                      T* znl, int steps, int n_l, int bs, hipStream_t s);
 
+// Nodal lumping option: y_out = y_in + scale * M x and w_out = scale * M x
+// per node of bs consecutive rows (M: row-major bs x bs blocks, applied
+// transposed with trans); y_in null reads as zero, either output may be
+// null, y_in may alias y_out.
+template <typename T>
+void node_apply(const T* M, const T* x, T scale, const T* y_in, T* y_out, T* w_out, int n, int bs, bool trans,
+                hipStream_t s);
+
+// y = b - a * (A x) over A's n rows (b null: zero).
+template <typename T>
+void spmv_axpy(const DCSR<T>& A, const T* x, T a, const T* b, T* y, int n, hipStream_t s);
+
 // zn_u[i] -= alpha * ainv[i] * (G delta)[i] for the listed rows of G.
 template <typename T>
 void correct_u(const DCSR<T>& G, const int32_t* rows, int n_rows, const T* delta, const T* ainv, T alpha, T* znu,

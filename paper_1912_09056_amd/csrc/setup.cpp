@@ -493,6 +493,237 @@ HostCSR schur_matrix(const HostLevel& L) {
   return out;
 }
 
+// In-place Gauss-Jordan inverse of a small dense row-major matrix with
+// partial pivoting; false when a pivot is exactly zero.
+bool invert_small(const double* a_in, double* inv, int bs) {
+  double a[6][12] = {};
+  for (int r = 0; r < bs; ++r) {
+    for (int c = 0; c < bs; ++c) a[r][c] = a_in[r * bs + c];
+    a[r][bs + r] = 1.0;
+  }
+  for (int c = 0; c < bs; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < bs; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+    if (a[piv][c] == 0.0) return false;
+    if (piv != c)
+      for (int k = 0; k < 2 * bs; ++k) std::swap(a[c][k], a[piv][k]);
+    const double d = 1.0 / a[c][c];
+    for (int k = 0; k < 2 * bs; ++k) a[c][k] *= d;
+    for (int r = 0; r < bs; ++r) {
+      if (r == c || a[r][c] == 0.0) continue;
+      const double f = a[r][c];
+      for (int k = 0; k < 2 * bs; ++k) a[r][k] -= f * a[c][k];
+    }
+  }
+  for (int r = 0; r < bs; ++r)
+    for (int c = 0; c < bs; ++c) inv[r * bs + c] = a[r][bs + c];
+  return true;
+}
+
+// Inverse nodal lumping blocks (scale * (K_ii + sum_{j != i} ||K_ij||_F I))^-1
+// per node of bs consecutive dofs, row-major, n_u * bs values.  For symmetric
+// K the blocks bound x^T K x from above (the block analogue of the row-sum
+// bound), and a rotation of the node frames maps them to R A_i R^T.
+std::vector<double> nodal_lumping_inverse(const HostCSR& K, int bs, double scale) {
+  const int64_t n = K.nrows;
+  if (bs < 1 || bs > 6 || n % bs) fail(kErrShape, "nodal lumping: node block size must be 1..6 and divide n_u");
+  const int64_t nb = n / bs;
+  std::vector<double> out((size_t)(n * bs));
+  constexpr int64_t kNodesPerChunk = 2048;
+  const int64_t n_chunks = (nb + kNodesPerChunk - 1) / kNodesPerChunk;
+  const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n_chunks, 1));
+  std::vector<std::vector<double>> sqs((size_t)nt);
+  parallel_chunks(n_chunks, nt, [&](int64_t c, int t) {
+    std::vector<double>& sq = sqs[(size_t)t];
+    if (sq.empty()) sq.assign((size_t)nb, 0.0);
+    std::vector<int64_t> touched;
+    const int64_t a1 = std::min(nb, (c + 1) * kNodesPerChunk);
+    for (int64_t a = c * kNodesPerChunk; a < a1; ++a) {
+      double blk[36] = {};
+      touched.clear();
+      for (int r = 0; r < bs; ++r) {
+        const int64_t i = a * bs + r;
+        for (int64_t k = K.rp[i]; k < K.rp[i + 1]; ++k) {
+          const int64_t b = K.ci[k] / bs;
+          if (b == a) {
+            blk[r * bs + K.ci[k] % bs] += K.v[k];
+          } else {
+            if (sq[(size_t)b] == 0.0) touched.push_back(b);
+            sq[(size_t)b] += K.v[k] * K.v[k];
+          }
+        }
+      }
+      std::sort(touched.begin(), touched.end());
+      double off = 0.0;
+      for (int64_t b : touched) {
+        off += std::sqrt(sq[(size_t)b]);
+        sq[(size_t)b] = 0.0;
+      }
+      for (int r = 0; r < bs; ++r) {
+        blk[r * bs + r] += off;
+        for (int q = 0; q < bs; ++q) blk[r * bs + q] *= scale;
+      }
+      if (!invert_small(blk, &out[(size_t)(a * bs * bs)], bs)) fail(kErrZeroDiag, "singular nodal lumping block");
+    }
+  });
+  return out;
+}
+
+// P = P_tent - omega Atilde^-1 K P_tent with the inverse nodal lumping blocks,
+// on the pattern of P_tent plus that of Atilde^-1 K P_tent (rows of a node
+// share the union of their K P_tent patterns).
+HostCSR smooth_prolongator_nodal(const HostCSR& K, const HostCSR& Pt, double omega, const std::vector<double>& ainv,
+                                 int bs) {
+  HostCSR out;
+  out.init_empty(K.nrows, Pt.ncols);
+  const int64_t nb = K.nrows / bs;
+  constexpr int64_t kNodesPerChunk = 1024;
+  const int64_t n_chunks = (nb + kNodesPerChunk - 1) / kNodesPerChunk;
+  std::vector<RowBlock> blocks((size_t)n_chunks);
+  const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n_chunks, 1));
+  std::vector<std::vector<int32_t>> locs((size_t)nt);
+  parallel_chunks(n_chunks, nt, [&](int64_t c, int t) {
+    std::vector<int32_t>& loc = locs[(size_t)t];
+    if (loc.empty()) loc.assign((size_t)Pt.ncols, -1);
+    std::vector<int32_t> cols, rowcols;
+    std::vector<double> kp;
+    RowBlock& blk = blocks[(size_t)c];
+    const int64_t a1 = std::min(nb, (c + 1) * kNodesPerChunk);
+    for (int64_t a = c * kNodesPerChunk; a < a1; ++a) {
+      const size_t nc = gather_pattern(cols, loc, [&](auto add) {
+        for (int r = 0; r < bs; ++r) {
+          const int64_t i = a * bs + r;
+          for (int64_t q = Pt.rp[i]; q < Pt.rp[i + 1]; ++q) add(Pt.ci[q]);
+          for (int64_t k = K.rp[i]; k < K.rp[i + 1]; ++k)
+            for (int64_t q = Pt.rp[K.ci[k]]; q < Pt.rp[K.ci[k] + 1]; ++q) add(Pt.ci[q]);
+        }
+      });
+      // (K P_tent) rows of the node on the union pattern; inkp marks the
+      // columns of that product's pattern
+      kp.assign(nc * (size_t)bs, 0.0);
+      std::vector<char> inkp(nc, 0), inrow(nc, 0);
+      for (int r = 0; r < bs; ++r) {
+        const int64_t i = a * bs + r;
+        for (int64_t k = K.rp[i]; k < K.rp[i + 1]; ++k) {
+          const int32_t j = K.ci[k];
+          for (int64_t q = Pt.rp[j]; q < Pt.rp[j + 1]; ++q) {
+            const size_t u = (size_t)loc[Pt.ci[q]];
+            kp[(size_t)r * nc + u] += K.v[k] * Pt.v[q];
+            inkp[u] = 1;
+          }
+        }
+      }
+      const double* M = &ainv[(size_t)(a * bs * bs)];
+      std::vector<double> val(nc);
+      for (int r = 0; r < bs; ++r) {
+        const int64_t i = a * bs + r;
+        std::fill(val.begin(), val.end(), 0.0);
+        std::fill(inrow.begin(), inrow.end(), 0);
+        for (int64_t q = Pt.rp[i]; q < Pt.rp[i + 1]; ++q) {
+          val[(size_t)loc[Pt.ci[q]]] = Pt.v[q];
+          inrow[(size_t)loc[Pt.ci[q]]] = 1;
+        }
+        for (int rr = 0; rr < bs; ++rr) {
+          const double m = omega * M[r * bs + rr];
+          if (m == 0.0) continue;
+          for (size_t u = 0; u < nc; ++u) val[u] -= m * kp[(size_t)rr * nc + u];
+        }
+        int64_t len = 0;
+        for (size_t u = 0; u < nc; ++u) {
+          if (!inkp[u] && !inrow[u]) continue;  // row pattern: P_tent's row plus the node's K P_tent pattern
+          blk.ci.push_back(cols[u]);
+          blk.v.push_back(val[u]);
+          ++len;
+        }
+        blk.len.push_back(len);
+      }
+      for (size_t u = 0; u < nc; ++u) loc[cols[u]] = -1;
+    }
+  });
+  append_blocks(out, blocks);
+  return out;
+}
+
+// B Atilde^-1 G - C with the inverse nodal lumping blocks, on the pattern of
+// B Atilde^-1 G (every dof of a node B touches) plus C's.
+HostCSR schur_matrix_nodal(const HostLevel& L, const std::vector<double>& ainv, int bs) {
+  const int64_t nl = L.n_l();
+  HostCSR out;
+  out.init_empty(nl, nl);
+  std::vector<int32_t> loc((size_t)nl, -1), cols;
+  std::vector<double> acc;
+  for (int64_t j = 0; j < nl; ++j) {
+    const size_t nc = gather_pattern(cols, loc, [&](auto add) {
+      for (int64_t k = L.B.rp[j]; k < L.B.rp[j + 1]; ++k) {
+        const int64_t a = L.B.ci[k] / bs;
+        for (int64_t i2 = a * bs; i2 < (a + 1) * bs; ++i2)
+          for (int64_t q = L.G.rp[i2]; q < L.G.rp[i2 + 1]; ++q) add(L.G.ci[q]);
+      }
+      for (int64_t q = L.C.rp[j]; q < L.C.rp[j + 1]; ++q) add(L.C.ci[q]);
+    });
+    acc.assign(nc, 0.0);
+    for (int64_t k = L.B.rp[j]; k < L.B.rp[j + 1]; ++k) {
+      const int64_t i = L.B.ci[k], a = i / bs;
+      const double* M = &ainv[(size_t)(a * bs * bs + (i % bs) * bs)];
+      for (int c = 0; c < bs; ++c) {
+        const double bk = L.B.v[k] * M[c];
+        const int64_t i2 = a * bs + c;
+        for (int64_t q = L.G.rp[i2]; q < L.G.rp[i2 + 1]; ++q) acc[(size_t)loc[L.G.ci[q]]] += bk * L.G.v[q];
+      }
+    }
+    for (int64_t q = L.C.rp[j]; q < L.C.rp[j + 1]; ++q) acc[(size_t)loc[L.C.ci[q]]] -= L.C.v[q];
+    for (size_t t = 0; t < nc; ++t) {
+      out.ci.push_back(cols[t]);
+      out.v.push_back(acc[t]);
+      loc[cols[t]] = -1;
+    }
+    out.rp[j + 1] = out.nnz();
+  }
+  return out;
+}
+
+// Relaxation data of the Schur system from S: inverse nodal blocks
+// (schur = 2), else the inverse diagonal (schur = 0) or signed l1 row sums
+// (schur = 1); S itself is kept for schur_sweeps > 1.
+void schur_relaxation(HostLevel& L, HostCSR S, const SetupOptions& opt) {
+  const int64_t nl = L.n_l();
+  L.sd_inv.assign((size_t)nl, 0.0);
+  L.sblk_inv.clear();
+  if (opt.schur == 2) {
+    // nodal block Jacobi: inverses of S's bs_l x bs_l diagonal blocks (the
+    // multipliers of one node are consecutive)
+    const int bs = L.bs_l;
+    if (bs <= 0 || bs > 3 || nl % bs) fail(kErrShape, "multiplier count is not a multiple of the node block size");
+    for (int64_t j = 0; j < (int64_t)L.lm_node.size(); ++j)
+      if (L.lm_node[(size_t)j] != j / bs) fail(kErrShape, "block Schur relaxation needs node-contiguous multipliers");
+    L.sblk_inv.assign((size_t)(nl * bs), 0.0);
+    for (int64_t nd = 0; nd < nl / bs; ++nd) {
+      double a[9] = {};
+      for (int r = 0; r < bs; ++r) {
+        const int64_t j = nd * bs + r;
+        for (int64_t k = S.rp[j]; k < S.rp[j + 1]; ++k) {
+          const int64_t c = S.ci[k] - nd * bs;
+          if (c >= 0 && c < bs) a[r * bs + c] = S.v[k];
+        }
+      }
+      if (!invert_small(a, &L.sblk_inv[(size_t)(nd * bs * bs)], bs)) fail(kErrZeroDiag, "singular Schur node block");
+    }
+  } else {
+    for (int64_t j = 0; j < nl; ++j) {
+      double d = 0.0, l1 = 0.0;
+      for (int64_t k = S.rp[j]; k < S.rp[j + 1]; ++k) {
+        l1 += std::fabs(S.v[k]);
+        if (S.ci[k] == j) d = S.v[k];
+      }
+      const double sd = opt.schur == 1 ? (d > 0.0 ? l1 : (d < 0.0 ? -l1 : 0.0)) : d;
+      if (sd == 0.0) fail(kErrZeroDiag, "zero diagonal of the Schur approximation");
+      L.sd_inv[(size_t)j] = 1.0 / sd;
+    }
+  }
+  if (opt.schur_sweeps > 1) L.S = std::move(S);
+}
+
 void smoother_data(HostLevel& L, const SetupOptions& opt) {
   const int64_t nu = L.n_u(), nl = L.n_l();
   std::vector<double> at((size_t)nu), dg((size_t)nu, 0.0);
@@ -504,10 +735,22 @@ void smoother_data(HostLevel& L, const SetupOptions& opt) {
     }
     at[i] = s;
   }
+  for (int64_t i = 0; i < nu; ++i)
+    if (dg[i] == 0.0) fail(kErrZeroDiag, "zero diagonal entry in K");
+  L.ablk_inv.clear();
+  if (opt.atilde == 2) {
+    // nodal lumping: its blocks relax the prediction, back-substitute and
+    // form S; Braess-Sarazin folds its alpha into them
+    const int bs = L.bs_u;
+    L.ablk_inv = nodal_lumping_inverse(L.K, bs, opt.bs_alpha > 0.0 ? opt.bs_alpha : 1.0);
+    L.atilde_inv.assign((size_t)nu, 0.0);  // the point vectors are unused
+    L.jac_inv.assign((size_t)nu, 0.0);
+    schur_relaxation(L, schur_matrix_nodal(L, L.ablk_inv, bs), opt);
+    return;
+  }
   L.atilde_inv.resize((size_t)nu);
   L.jac_inv.resize((size_t)nu);
   for (int64_t i = 0; i < nu; ++i) {
-    if (dg[i] == 0.0) fail(kErrZeroDiag, "zero diagonal entry in K");
     double a = opt.atilde == 0 ? at[i] : dg[i];
     if (a == 0.0) fail(kErrZeroDiag, "zero SIMPLEC lumping");
     if (opt.bs_alpha > 0.0) {
@@ -524,61 +767,8 @@ void smoother_data(HostLevel& L, const SetupOptions& opt) {
   }
   L.sd_inv.resize((size_t)nl);
   L.sblk_inv.clear();
-  if (opt.schur == 2) {
-    // nodal block Jacobi: inverses of S's bs_l x bs_l diagonal blocks (the
-    // multipliers of one node are consecutive)
-    const int bs = L.bs_l;
-    if (bs <= 0 || bs > 3 || nl % bs) fail(kErrShape, "multiplier count is not a multiple of the node block size");
-    for (int64_t j = 0; j < (int64_t)L.lm_node.size(); ++j)
-      if (L.lm_node[(size_t)j] != j / bs) fail(kErrShape, "block Schur relaxation needs node-contiguous multipliers");
-    HostCSR S = schur_matrix(L);
-    L.sblk_inv.assign((size_t)(nl * bs), 0.0);
-    for (int64_t nd = 0; nd < nl / bs; ++nd) {
-      double a[4][8] = {};
-      for (int r = 0; r < bs; ++r) {
-        const int64_t j = nd * bs + r;
-        for (int64_t k = S.rp[j]; k < S.rp[j + 1]; ++k) {
-          const int64_t c = S.ci[k] - nd * bs;
-          if (c >= 0 && c < bs) a[r][c] = S.v[k];
-        }
-        a[r][bs + r] = 1.0;
-      }
-      // Gauss-Jordan with partial pivoting on [A | I]
-      for (int c = 0; c < bs; ++c) {
-        int piv = c;
-        for (int r = c + 1; r < bs; ++r)
-          if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
-        if (a[piv][c] == 0.0) fail(kErrZeroDiag, "singular Schur node block");
-        if (piv != c)
-          for (int k = 0; k < 2 * bs; ++k) std::swap(a[c][k], a[piv][k]);
-        const double inv = 1.0 / a[c][c];
-        for (int k = 0; k < 2 * bs; ++k) a[c][k] *= inv;
-        for (int r = 0; r < bs; ++r) {
-          if (r == c || a[r][c] == 0.0) continue;
-          const double f = a[r][c];
-          for (int k = 0; k < 2 * bs; ++k) a[r][k] -= f * a[c][k];
-        }
-      }
-      for (int r = 0; r < bs; ++r)
-        for (int c = 0; c < bs; ++c) L.sblk_inv[(size_t)((nd * bs + r) * bs + c)] = a[r][bs + c];
-    }
-    for (int64_t j = 0; j < nl; ++j) L.sd_inv[(size_t)j] = 0.0;  // unused: the blocks relax
-    if (opt.schur_sweeps > 1) L.S = std::move(S);
-    return;
-  }
-  if (opt.schur == 1 || opt.schur_sweeps > 1) {
-    HostCSR S = schur_matrix(L);
-    for (int64_t j = 0; j < nl; ++j) {
-      double d = 0.0, l1 = 0.0;
-      for (int64_t k = S.rp[j]; k < S.rp[j + 1]; ++k) {
-        l1 += std::fabs(S.v[k]);
-        if (S.ci[k] == j) d = S.v[k];
-      }
-      const double sd = opt.schur == 1 ? (d > 0.0 ? l1 : (d < 0.0 ? -l1 : 0.0)) : d;
-      if (sd == 0.0) fail(kErrZeroDiag, "zero diagonal of the Schur approximation");
-      L.sd_inv[j] = 1.0 / sd;
-    }
-    if (opt.schur_sweeps > 1) L.S = std::move(S);
+  if (opt.schur == 2 || opt.schur == 1 || opt.schur_sweeps > 1) {
+    schur_relaxation(L, schur_matrix(L), opt);
     return;
   }
   // S_d[j] = sum_i B[j,i] G[i,j] / Atilde_i - C[j,j]
@@ -683,7 +873,10 @@ HostLevel coarsen(HostLevel& L, const SetupOptions& opt) {
   tentative(
       L.n_l(), L.n_ns_l, L.ns_l, L.agg_l, L.n_agg_l, [&](int64_t r) { return (int64_t)L.lm_node[r]; },
       [&](int64_t) { return false; }, L.P_l, nsc_l);
-  if (opt.prolongator == 1) L.P_u = smooth_prolongator(L.K, L.P_u, opt.sa_omega);
+  if (opt.prolongator == 1)
+    L.P_u = opt.atilde == 2 ? smooth_prolongator_nodal(L.K, L.P_u, opt.sa_omega,
+                                                       nodal_lumping_inverse(L.K, L.bs_u, 1.0), L.bs_u)
+                            : smooth_prolongator(L.K, L.P_u, opt.sa_omega);
   HostCSR Ru = transpose(L.P_u), Rl = transpose(L.P_l);
   Cn.K = galerkin(Ru, L.K, L.P_u);
   Cn.G = galerkin(Ru, L.G, L.P_l);

@@ -42,6 +42,7 @@ struct HostLevel {
   HostCSR P_u, P_l;
   std::vector<double> atilde_inv, jac_inv, sd_inv;
   std::vector<double> sblk_inv;    // block Schur option: inverse nodal blocks, bs_l x bs_l row-major each
+  std::vector<double> ablk_inv;    // nodal lumping option: inverse blocks, bs_u x bs_u row-major each
   HostCSR S;                       // B Atilde^-1 G - C (only when relaxed by Jacobi sweeps)
   std::vector<double> Ainv;        // coarsest level with the direct solve: dense inverse, row-major
   int64_t n_u() const { return K.nrows; }
@@ -53,7 +54,7 @@ struct HostLevel {
 struct SetupOptions {
   int max_levels = 4;
   int max_coarse_rows = 1000;
-  int atilde = 0;       // 0 row sums of |K|, 1 diag(K)
+  int atilde = 0;       // 0 row sums of |K|, 1 diag(K), 2 nodal blocks
   int jacobi_diag = 0;  // 0 Atilde, 1 diag(K)
   int prolongator = 0;  // 0 tentative, 1 smoothed (displacement transfers)
   double sa_omega = 4.0 / 3.0;

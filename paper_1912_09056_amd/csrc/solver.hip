@@ -187,6 +187,7 @@ struct LevelVecs {
   DBuf<T> delta2, qrhs;  // Schur sweeps: second delta buffer and right-hand side
   DBuf<T> jinv, ainv, sdinv;
   DBuf<T> sblk;  // block Schur option: inverse nodal blocks of S (bs_l x bs_l, row-major)
+  DBuf<T> ablk;  // nodal lumping option: inverse lumping blocks (bs_u x bs_u, row-major)
   DBuf<T> Ainv, AinvT;
 };
 
@@ -196,6 +197,7 @@ struct DevLevel {
   DevMat S, ST;  // Schur matrix B Atilde^-1 G - C and its transpose (Schur sweeps only)
   int sg_S = 8;
   int sblk_bs = 0;     // > 0: the Schur step relaxes with nodal blocks of this size
+  int ablk_bs = 0;     // > 0: nodal lumping blocks of this size (the nodal sweep)
   bool bell = false;   // K and K^T in sliced blocked-ELL layout
   DevBell Kb, KTb;
   int64_t k_blocks = 0, k_slots = 0;
@@ -356,6 +358,7 @@ static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool dense_coarse, h
     up(V.ainv, H.atilde_inv);
     up(V.sdinv, H.sd_inv);
     if (!H.sblk_inv.empty()) up(V.sblk, H.sblk_inv);
+    if (!H.ablk_inv.empty()) up(V.ablk, H.ablk_inv);
   } else {
     up(V.Ainv, H.Ainv);
     std::vector<double> t(H.Ainv.size());
@@ -436,6 +439,7 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       D.g_rows.upload(gr, s);
     }
     D.sblk_bs = (!dense_coarse && !H.sblk_inv.empty()) ? H.bs_l : 0;
+    D.ablk_bs = (!dense_coarse && !H.ablk_inv.empty()) ? H.bs_u : 0;
     if (mixed) alloc_vecs<float>(D.v32, H, dense_coarse, s);
     else alloc_vecs<double>(D.v64, H, dense_coarse, s);
     if (mixed && l == 0) {
@@ -464,9 +468,100 @@ LevelVecs<float>& vecs<float>(DevLevel& D) {
   return D.v32;
 }
 
+// One sweep with the nodal lumping blocks M = Atilde^-1 (the option that
+// makes the smoothers covariant under rotations of the node frames), from
+// generic kernels: block applies per node instead of the fused point-diagonal
+// kernels.  Forward (SIMPLE; Uzawa and Braess-Sarazin as in sweep):
+//   t = b_u - K z_u - G z_l,  w = J(t) (block Jacobi with M),
+//   q = -(b_l - B (z_u + w) - C z_l),  delta = S-relaxation(q),
+//   zn_l = z_l + alpha delta,  zn_u = z_u + w - alpha M G delta.
+// Adjoint: s_u = b_u - K^T z_u - B^T z_l, q = -(b_l - G^T (z_u + M^T s_u) -
+// C^T z_l), delta from S^T, zn_u = z_u + J^T(s_u - alpha B^T delta) with M^T.
+// From z = 0 (first) the input buffer is cleared and the general form runs.
+template <typename T>
+static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const T* z, T* zn, bool first,
+                        hipStream_t s) {
+  DevLevel& D = h.lev[l];
+  LevelVecs<T>& V = vecs<T>(D);
+  const int nu = (int)D.n_u, nl = (int)D.n_l, bs = D.ablk_bs;
+  const bool uzawa = h.opts.smoother == CAMG_SMOOTHER_UZAWA;
+  const bool bsz = h.opts.smoother == CAMG_SMOOTHER_BRAESS_SARAZIN;
+  const T om = bsz ? T(1) : (T)h.opts.jacobi_omega;
+  const T al = bsz ? T(1) : (T)h.opts.simple_alpha;
+  const int nj = bsz ? 1 : std::max(1, h.opts.jacobi_sweeps);
+  const int ks = D.S.nrows > 0 ? std::max(1, h.opts.schur_sweeps) - 1 : 0;  // Jacobi sweeps on S after the first
+  const bool sblock = D.sblk_bs > 0;
+  T* q = V.qrhs.p;
+  const T* sdv = sblock ? nullptr : V.sdinv.p;
+  // the V-cycle passes its own work buffer as z; from zero it is cleared
+  if (first) zero_vec<T>(const_cast<T*>(z), D.n(), s);
+  const T* bu = b;
+  const T* bl = b + nu;
+  const T* zu = z;
+  const T* zl = z + nu;
+  T* znu = zn;
+  T* znl = zn + nu;
+  const T* M = V.ablk.p;
+  DCSR<T> none;
+  // delta from q = -(r_l - B w): the multiplier kernel already divided by the
+  // diagonal (point options) or only stored q (nodal Schur blocks)
+  auto schur = [&](const DevMat& SM, bool trans) -> const T* {
+    if (sblock)
+      return schur_block_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sblk.p, trans, zl, al, znl, ks + 1, nl,
+                                  D.sblk_bs, s);
+    return schur_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, zl, al, znl, ks, nl, D.sg_S, s);
+  };
+  T* wa = V.aux2.p;
+  T* wb = V.su.p;
+  T* tr = V.r.p;  // r is free during a sweep
+  if (!transpose) {
+    T* t = V.aux1.p;
+    blk_spmv<T>(D.K.view<T>(), D.G.view<T>(), none, none, zu, zl, bu, nullptr, t, nullptr, nu, 0, 1, D.sg_K, s);
+    node_apply<T>(M, t, om, nullptr, nullptr, wa, nu, bs, false, s);
+    for (int k = 1; k < nj; ++k) {
+      blk_spmv<T>(D.K.view<T>(), none, none, none, wa, nullptr, t, nullptr, tr, nullptr, nu, 0, 1, D.sg_K, s);
+      node_apply<T>(M, tr, om, wa, wb, nullptr, nu, bs, false, s);
+      std::swap(wa, wb);
+    }
+    uzawa_update<T>(zu, wa, T(1), znu, nu, s);  // zn_u = z_u + w
+    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, sdv, al, znl, V.delta.p, q, nl, false, s);
+    const T* dfin = schur(D.S, false);
+    if (uzawa) {
+      uzawa_update<T>(zu, wa, al, znu, nu, s);
+    } else {
+      spmv_axpy<T>(D.G.view<T>(), dfin, T(-1), nullptr, tr, nu, s);  // G delta
+      node_apply<T>(M, tr, -al, znu, znu, nullptr, nu, bs, false, s);
+    }
+  } else {
+    T* su = V.aux1.p;
+    tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, su, nu, false, D.sg_K, s);
+    const T* y = zu;
+    if (!uzawa) {
+      node_apply<T>(M, su, T(1), zu, tr, nullptr, nu, bs, true, s);  // z_u + M^T s_u
+      y = tr;
+    }
+    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), y, zl, bl, su, nullptr, sdv, al, znl, V.delta.p, q, nl, false, s);
+    const T* dfin = schur(D.ST, true);
+    T* t = tr;
+    spmv_axpy<T>(D.BT.view<T>(), dfin, uzawa ? T(1) : al, su, t, nu, s);  // s_u - a B^T delta
+    node_apply<T>(M, t, om, nullptr, nullptr, wa, nu, bs, true, s);
+    T* tk = su;  // s_u is no longer needed
+    for (int k = 1; k < nj; ++k) {
+      blk_spmv<T>(D.KT.view<T>(), none, none, none, wa, nullptr, t, nullptr, tk, nullptr, nu, 0, 1, D.sg_K, s);
+      node_apply<T>(M, tk, om, wa, wb, nullptr, nu, bs, true, s);
+      std::swap(wa, wb);
+    }
+    uzawa_update<T>(zu, wa, uzawa ? al : T(1), znu, nu, s);
+  }
+}
+
 template <typename T>
 static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, T* zn, bool first, hipStream_t s) {
   DevLevel& D = h.lev[l];
+  if (D.ablk_bs > 0) {
+    sweep_nodal<T>(h, l, transpose, b, z, zn, first, s);
+    return;
+  }
   LevelVecs<T>& V = vecs<T>(D);
   const int nu = (int)D.n_u, nl = (int)D.n_l;
   // Braess-Sarazin runs the CheapSIMPLE kernels on its scaled lumping with
@@ -960,7 +1055,8 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   if (opts) o = *opts;
   if (p->dim < 1 || p->dim > 3) api_fail(CAMG_ERR_INVALID_ARG, "dim must be 1..3");
   if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
-      (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 1 ||
+      (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 2 ||
+      (o.atilde == CAMG_ATILDE_NODAL && o.jacobi_diag != CAMG_JACOBI_ATILDE) ||
       o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
       o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 2 || o.schur_sweeps < 1 ||
       o.schur_sweeps > 64 || !(o.sa_omega > 0.0) || !std::isfinite(o.sa_omega) || o.coarse_solver < 0 ||
@@ -1123,22 +1219,26 @@ int amg_get_aggregates(const amg_handle* h, int level, int32_t* disp_agg, int32_
 int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nrows, int64_t* ncols, int64_t* nnz,
                          int64_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> int {
-    if (!h || level < 0 || level >= (int)h->host.size() || which < 0 || which > 7)
+    if (!h || level < 0 || level >= (int)h->host.size() || which < 0 || which > 8)
       api_fail(CAMG_ERR_INVALID_ARG, "level/which");
     const HostLevel& L = h->host[level];
-    HostCSR blk;  // which = 7: the inverse nodal Schur blocks as a block-diagonal matrix
-    if (which == 7 && !L.sblk_inv.empty()) {
-      const int bs = L.bs_l;
-      const int64_t nl = L.n_l();
-      blk.nrows = blk.ncols = nl;
-      blk.rp.resize((size_t)nl + 1);
-      for (int64_t j = 0; j <= nl; ++j) blk.rp[(size_t)j] = j * bs;
-      blk.ci.resize((size_t)(nl * bs));
-      for (int64_t j = 0; j < nl; ++j)
+    // which = 7 / 8: the inverse nodal Schur / lumping blocks as a block-diagonal matrix
+    auto block_diag = [](const std::vector<double>& v, int bs, int64_t n) {
+      HostCSR blk;
+      if (v.empty()) return blk;
+      blk.nrows = blk.ncols = n;
+      blk.rp.resize((size_t)n + 1);
+      for (int64_t j = 0; j <= n; ++j) blk.rp[(size_t)j] = j * bs;
+      blk.ci.resize((size_t)(n * bs));
+      for (int64_t j = 0; j < n; ++j)
         for (int c = 0; c < bs; ++c) blk.ci[(size_t)(j * bs + c)] = (int32_t)((j / bs) * bs + c);
-      blk.v = L.sblk_inv;
-    }
-    const HostCSR* M[8] = {&L.K, &L.G, &L.B, &L.C, &L.P_u, &L.P_l, &L.S, &blk};
+      blk.v = v;
+      return blk;
+    };
+    HostCSR blk;
+    if (which == 7) blk = block_diag(L.sblk_inv, L.bs_l, L.n_l());
+    if (which == 8) blk = block_diag(L.ablk_inv, L.bs_u, L.n_u());
+    const HostCSR* M[9] = {&L.K, &L.G, &L.B, &L.C, &L.P_u, &L.P_l, &L.S, &blk, &blk};
     if ((which == 4 || which == 5) && level + 1 >= (int)h->host.size())
       api_fail(CAMG_ERR_INVALID_ARG, "no transfer on coarsest");
     const HostCSR& A = *M[which];

@@ -508,6 +508,77 @@ def test_block_schur_on_rotated_problem(fmt, which):
             assert abs(info["iters"] - ref.iters) <= 1
 
 
+NODAL = [
+    (dict(simple_alpha=0.7, jacobi_omega=0.7), dict(simple_alpha=0.7, jacobi_omega=0.7)),
+    (dict(simple_alpha=0.7, jacobi_omega=0.7, jacobi_sweeps=2, schur_sweeps=3, prolongator="sa"),
+     dict(simple_alpha=0.7, jacobi_omega=0.7, jacobi_sweeps=2, schur_sweeps=3, prolongator=1)),
+    (dict(smoother="uzawa", simple_alpha=0.7, jacobi_omega=0.7, jacobi_sweeps=2),
+     dict(smoother=1, simple_alpha=0.7, jacobi_omega=0.7, jacobi_sweeps=2)),
+    (dict(smoother="braess_sarazin", simple_alpha=1.9), dict(smoother=2, simple_alpha=1.9)),
+    (dict(simple_alpha=0.7, jacobi_omega=0.7, schur="l1", schur_sweeps=2),
+     dict(simple_alpha=0.7, jacobi_omega=0.7, schur=1, schur_sweeps=2)),
+]
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+@pytest.mark.parametrize("which", range(len(NODAL)))
+def test_nodal_lumping_on_rotated_problem(fmt, which):
+    """Nodal lumping blocks (block Jacobi prediction, block back-substitution,
+    Schur matrix and smoothed prolongator from them) on a rigidly rotated
+    clamped problem, three levels: V-cycle and its transpose (FP64 1e-12,
+    mixed 2e-5), fixed-iteration FGMRES (1e-10) and a converged solve against
+    the oracle."""
+    okw, lkw = NODAL[which]
+    okw = dict({"schur": "block"}, **okw)
+    lkw = dict({"schur": 2}, **lkw)
+    prob = _rotated_clamped((0.3, 1.1))
+    kw = dict(max_levels=3, max_coarse_rows=50, nu_pre=3, nu_post=3)
+    oopts = OracleOptions(**kw, atilde="nodal", **okw)
+    lv = build_hierarchy(prob, oopts)
+    r = np.random.default_rng(22).standard_normal(prob.n)
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        s = _solver(prob, precision=prec, fmt=fmt, atilde=2, **kw, **lkw)
+        for tr in (False, True):
+            z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+            assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < tol, (okw, prec, tr)
+    s = _solver(prob, fmt=fmt, atilde=2, **kw, **lkw)
+    for tr in (False, True):
+        ref = oracle_solve(lv, oopts, prob.b, transpose=tr, m=10, fixed_iters=20)
+        x, info = s.solve(torch.from_numpy(prob.b), transpose=tr, m=10, fixed_iters=20)
+        assert _rel(x.cpu().numpy(), ref.x) < 1e-10, (okw, tr)
+    ref = oracle_solve(lv, oopts, prob.b, rtol=1e-8, max_iters=300)
+    A = prob.full_matrix()
+    for prec in (0, 1):
+        s = _solver(prob, precision=prec, fmt=fmt, atilde=2, **kw, **lkw)
+        x, info = s.solve(torch.from_numpy(prob.b), rtol=1e-8, max_iters=300)
+        print(f"[nodal] {okw} fmt={fmt} prec={prec} iters={info['iters']} oracle={ref.iters}", flush=True)
+        assert info["converged"], (okw, prec, info)
+        assert np.linalg.norm(prob.b - A @ x.cpu().numpy()) <= 1.0001e-8 * np.linalg.norm(prob.b)
+        if prec == 0:
+            assert abs(info["iters"] - ref.iters) <= 1
+
+
+def test_nodal_lumping_iterations_do_not_depend_on_the_angles():
+    """The rotation experiment at the paper's size with the nodal lumping and
+    nodal Schur blocks: each smoother's FP64 iteration count is the same for
+    every rotation (within one iteration of rounding)."""
+    kw = dict(max_levels=3, max_coarse_rows=50, nu_pre=3, nu_post=3, atilde=2, schur=2)
+    sm = {0: dict(smoother=0, simple_alpha=0.7, jacobi_omega=0.7), 1: dict(smoother=1, simple_alpha=0.7,
+                                                                          jacobi_omega=0.7),
+          2: dict(smoother=2, simple_alpha=1.9)}
+    its = {k: [] for k in sm}
+    for ang in [(0.0, 0.0), (np.pi / 8, np.pi / 4), (3 * np.pi / 8, np.pi / 8), (np.pi / 2, 3 * np.pi / 8)]:
+        prob = _rotated_clamped(ang, (9, 9, 9), (9, 9, 9))
+        b = torch.from_numpy(prob.b)
+        for k, skw in sm.items():
+            x, info = _solver(prob, precision=0, **kw, **skw).solve(b, rtol=1e-8, max_iters=300)
+            assert info["converged"], (k, ang, info)
+            its[k].append(info["iters"])
+    print(f"[rotation-nodal] {its}", flush=True)
+    for k, v in its.items():
+        assert max(v) - min(v) <= 1, (k, v)
+
+
 def test_rotation_insensitive_iterations_with_block_schur():
     """The two-body rotation experiment at the paper's size (two 10x10x10
     node blocks, 6300 unknowns; three levels, three CheapSIMPLE(0.7) sweeps):

@@ -250,3 +250,49 @@ def test_host_block_schur_matches_oracle(smoother):
     # the diagonal options keep no blocks
     lib0 = AMGSolver.from_problem(prob, AMGOptions(max_levels=2, max_coarse_rows=50, schur=1), host_only=True)
     assert lib0.level_matrix(0, "Sblk_inv").shape == (0, 0)
+
+
+@pytest.mark.parametrize("smoother,prolongator", [(0, 0), (0, 1), (1, 1), (2, 0)])
+def test_host_nodal_lumping_matches_oracle(smoother, prolongator):
+    # nodal lumping blocks, the smoothed prolongator and the Schur matrix
+    # formed with them, and the nodal Schur blocks (of S_a for
+    # Braess-Sarazin, whose alpha the library folds into its lumping blocks)
+    import scipy.sparse as sp
+
+    from contactgen import rotate_problem
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
+
+    p = make_contact_problem(3, (4, 4, 3), (5, 5, 3), slave_box=((0.1, 0.1, 0.0), (0.8, 0.8, 0.5)),
+                             master_box=((0.0, 0.0, -1.0), (1.0, 1.0, 1.0)), top_bc="clamped", rhs="gap",
+                             penetration=0.01)
+    prob = rotate_problem(p, 0.3, 1.1)
+    names = {0: "simple", 1: "uzawa", 2: "braess_sarazin"}
+    al = 1.9 if smoother == 2 else 0.7
+    ora = build_hierarchy(prob, OracleOptions(max_levels=3, max_coarse_rows=50, atilde="nodal", schur="block",
+                                              schur_sweeps=2, smoother=names[smoother], simple_alpha=al,
+                                              prolongator="sa" if prolongator else "pa"))
+    lib = AMGSolver.from_problem(prob, AMGOptions(max_levels=3, max_coarse_rows=50, atilde=2, schur=2, schur_sweeps=2,
+                                                  smoother=smoother, simple_alpha=al, prolongator=prolongator),
+                                 host_only=True)
+    assert lib.n_levels == len(ora) == 3
+    for l, L in enumerate(ora[:-1]):
+        for blk in ("K", "G", "B", "C", "P_u", "P_l"):
+            A, R = lib.level_matrix(l, blk), getattr(L, blk)
+            assert np.array_equal(A.indptr, R.indptr) and np.array_equal(A.indices, R.indices), (l, blk)
+            scale = max(1.0, np.abs(R.data).max()) if R.nnz else 1.0
+            assert np.abs(A.data - R.data).max(initial=0.0) <= 1e-12 * scale, (l, blk)
+        S_ref = L.extra["bs_S"] if smoother == 2 else L.S
+        S = lib.level_matrix(l, "S")
+        assert np.array_equal(S.indptr, S_ref.indptr) and np.array_equal(S.indices, S_ref.indices), l
+        assert np.abs(S.data - S_ref.data).max() <= 1e-12 * np.abs(S_ref.data).max(), l
+        Ab = lib.level_matrix(l, "Ablk_inv").toarray()
+        ref = sp.block_diag(list(L.atilde_inv / (al if smoother == 2 else 1.0))).toarray()
+        assert np.abs(Ab - ref).max() <= 1e-11 * np.abs(ref).max(), l
+        Sb = lib.level_matrix(l, "Sblk_inv").toarray()
+        ref = sp.block_diag(list(L.extra["bs_sb_inv" if smoother == 2 else "sb_inv"])).toarray()
+        assert np.abs(Sb - ref).max() <= 1e-10 * np.abs(ref).max(), l
+    from paper_1912_09056_amd.camg import CamgError
+
+    with pytest.raises(CamgError) as e:  # the nodal blocks are the prediction's relaxation too
+        AMGSolver.from_problem(prob, AMGOptions(max_levels=2, atilde=2, jacobi_diag=1), host_only=True)
+    assert e.value.code == -1
