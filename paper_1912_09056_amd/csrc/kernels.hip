@@ -429,12 +429,15 @@ __global__ void __launch_bounds__(kBlock) k_schur_block(DCSR<T> S, const T* __re
 // Nodal lumping option, one thread per node j (BS consecutive dofs):
 //   v_j = scale * M_j x_j   (M_j^T x_j with TRANS; M row-major per node),
 //   w_out_j = v_j, y_out_j = y_in_j + v_j (y_in null: zero).
-// y_in may alias y_out (each thread reads its own rows first).
+// y_in may alias y_out (each thread reads its own rows first).  With list,
+// only the listed nodes (n_nodes of them).
 template <typename T, int BS, bool TRANS>
 __global__ void __launch_bounds__(kBlock) k_node_apply(const T* __restrict__ M, const T* __restrict__ x, T scale,
-                                                       const T* y_in, T* y_out, T* __restrict__ w_out, int n_nodes) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n_nodes) return;
+                                                       const T* y_in, T* y_out, T* __restrict__ w_out, int n_nodes,
+                                                       const int32_t* __restrict__ list) {
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= n_nodes) return;
+  const int j = list ? list[idx] : idx;
   const T* Mj = M + (size_t)j * (BS * BS);
   T xv[BS], v[BS];
 #pragma unroll
@@ -768,6 +771,108 @@ __global__ void k_jacobi_extra_bell(DBELL<T> M, const T* __restrict__ w, const T
   if (last) znu[row] = (zu ? zu[row] : T(0)) + wn;
 }
 
+// Nodal lumping option, level-0 layout: residual and block Jacobi prediction
+// in one pass.  The BS rows of a node sit in the BS waves of the workgroup
+// (lane = node in the slice, wave = row in the node); their residuals meet in
+// LDS and each row applies its row of the node's inverse lumping block M:
+//   t = b_u - K z_u - G z_l,  w = omega M t,  zn_u = z_u + w,
+// t_out / w_out optional.
+template <typename T, int BS>
+__global__ void k_smooth_u_bell_nodal(DBELL<T> K, DCSR<T> G, const T* __restrict__ zu, const T* __restrict__ zl,
+                                      const T* __restrict__ bu, const T* __restrict__ M, T omega,
+                                      T* __restrict__ znu, T* __restrict__ t_out, T* __restrict__ w_out) {
+  __shared__ T tl[BS][64];
+  const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
+  const int slice = blockIdx.x;
+  T s = bell_row<T, BS>(K, zu, slice, lane, a);
+  const int node = slice * 64 + lane;
+  const bool live = node < K.n_nodes;
+  const int row = node * BS + a;
+  T t = T(0);
+  if (live) {
+    if (G.nnz) s += csr_row_serial<T>(G, zl, row);
+    t = bu[row] - s;
+  }
+  tl[a][lane] = t;
+  __syncthreads();
+  if (!live) return;
+  const T* Mn = M + (size_t)node * (BS * BS) + a * BS;
+  T acc = T(0);
+#pragma unroll
+  for (int b = 0; b < BS; ++b) acc += Mn[b] * tl[b][lane];
+  const T w = omega * acc;
+  znu[row] = zu[row] + w;
+  if (t_out) t_out[row] = t;
+  if (w_out) w_out[row] = w;
+}
+
+// Nodal lumping option: back-substitution on the listed (interface) nodes,
+// zn_u += scale * M (G delta) per node.  One wave per node: row b of the node
+// takes lanes [b SGB, (b+1) SGB) for its G row dot (the interface rows are
+// short and their loads chain, so they are spread over lanes), then lanes
+// a < BS apply row a of M to the node's BS dots.
+template <typename T, int BS>
+__global__ void __launch_bounds__(kBlock) k_node_correct(DCSR<T> G, const int32_t* __restrict__ nodes, int n_list,
+                                                         const T* __restrict__ delta, const T* __restrict__ M,
+                                                         T scale, T* __restrict__ znu) {
+  constexpr int SGB = BS <= 2 ? 32 : (BS <= 4 ? 16 : 8);
+  static_assert(BS * SGB <= 64, "one wave per node");
+  const int wave = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= n_list) return;  // uniform across the wave
+  const int nd = nodes[wave];
+  const int b = lane / SGB, sl = lane % SGB;
+  T g = T(0);
+  if (b < BS) {
+    const int row = nd * BS + b;
+    const int e = G.rp[row + 1];
+    for (int k = G.rp[row] + sl; k < e; k += SGB) g += G.v[k] * delta[G.ci[k]];
+  }
+  g = sg_reduce<T, SGB>(g);
+  T gb[BS];
+#pragma unroll
+  for (int q = 0; q < BS; ++q) gb[q] = __shfl(g, q * SGB, 64);
+  if (lane < BS) {
+    const T* Mn = M + (size_t)nd * (BS * BS) + lane * BS;
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < BS; ++q) acc += Mn[q] * gb[q];
+    znu[(size_t)nd * BS + lane] += scale * acc;
+  }
+}
+
+// Nodal lumping option, adjoint update per node:
+//   t = s_u - a B^T delta,  w = omega M^T t,  zn_u = z_u + c w   (z_u null: zero)
+// t_out / w_out optional (extra Jacobi sweeps).
+template <typename T, int BS>
+__global__ void __launch_bounds__(kBlock) k_tcorrect_nodal(DCSR<T> BT, const T* __restrict__ su,
+                                                           const T* __restrict__ delta, const T* __restrict__ M,
+                                                           T omega, T a_bt, T c_w, const T* __restrict__ zu,
+                                                           T* __restrict__ znu, T* __restrict__ t_out,
+                                                           T* __restrict__ w_out, int n_nodes) {
+  const int nd = blockIdx.x * kBlock + threadIdx.x;
+  if (nd >= n_nodes) return;
+  T t[BS];
+#pragma unroll
+  for (int b = 0; b < BS; ++b) {
+    const int row = nd * BS + b;
+    t[b] = su[row];
+    if (BT.nnz) t[b] -= a_bt * csr_row_serial<T>(BT, delta, row);
+  }
+  const T* Mn = M + (size_t)nd * (BS * BS);
+#pragma unroll
+  for (int a = 0; a < BS; ++a) {
+    T acc = T(0);
+#pragma unroll
+    for (int b = 0; b < BS; ++b) acc += Mn[b * BS + a] * t[b];
+    const T w = omega * acc;
+    const size_t row = (size_t)nd * BS + a;
+    znu[row] = (zu ? zu[row] : T(0)) + c_w * w;
+    if (t_out) t_out[row] = t[a];
+    if (w_out) w_out[row] = w;
+  }
+}
+
 // ---- Krylov -----------------------------------------------------------------
 
 constexpr int kDotGroup = 8;
@@ -1077,16 +1182,17 @@ T* schur_block_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* blk,
 
 template <typename T>
 void node_apply(const T* M, const T* x, T scale, const T* y_in, T* y_out, T* w_out, int n, int bs, bool trans,
-                hipStream_t s) {
+                hipStream_t s, const int32_t* list, int n_list) {
   if (n <= 0) return;
   if (bs < 1 || bs > 6 || n % bs) throw std::runtime_error("node_apply: node block size must be 1..6 and divide n");
-  const int nn = n / bs;
+  const int nn = list ? n_list : n / bs;
+  if (nn <= 0) return;
   const unsigned g = grid_for(nn, kBlock);
 #define CAMG_NODE_APPLY_LAUNCH(BSV)                                                                     \
   if (trans)                                                                                            \
-    k_node_apply<T, BSV, true><<<g, kBlock, 0, s>>>(M, x, scale, y_in, y_out, w_out, nn);                \
+    k_node_apply<T, BSV, true><<<g, kBlock, 0, s>>>(M, x, scale, y_in, y_out, w_out, nn, list);          \
   else                                                                                                  \
-    k_node_apply<T, BSV, false><<<g, kBlock, 0, s>>>(M, x, scale, y_in, y_out, w_out, nn);
+    k_node_apply<T, BSV, false><<<g, kBlock, 0, s>>>(M, x, scale, y_in, y_out, w_out, nn, list);
   switch (bs) {
     case 1: CAMG_NODE_APPLY_LAUNCH(1) break;
     case 2: CAMG_NODE_APPLY_LAUNCH(2) break;
@@ -1313,6 +1419,54 @@ void jacobi_extra_bell(const DBELL<T>& M, const T* w, const T* r, const T* jinv,
   CAMG_LAUNCHED();
 }
 
+template <typename T>
+void smooth_u_bell_nodal(const DBELL<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* M,
+                         T omega, T* znu, T* t_out, T* w_out, int n_u, hipStream_t s) {
+  if (n_u <= 0) return;
+  if ((int64_t)K.n_nodes * K.bs != n_u) throw std::runtime_error("smooth_u_bell_nodal: layout does not match n_u");
+  switch (K.bs) {
+    case 2: k_smooth_u_bell_nodal<T, 2><<<K.n_slices, 128, 0, s>>>(K, G, zu, zl, bu, M, omega, znu, t_out, w_out); break;
+    case 3: k_smooth_u_bell_nodal<T, 3><<<K.n_slices, 192, 0, s>>>(K, G, zu, zl, bu, M, omega, znu, t_out, w_out); break;
+    case 6: k_smooth_u_bell_nodal<T, 6><<<K.n_slices, 384, 0, s>>>(K, G, zu, zl, bu, M, omega, znu, t_out, w_out); break;
+    default: throw std::runtime_error("smooth_u_bell_nodal: node block size must be 2, 3 or 6");
+  }
+  CAMG_LAUNCHED();
+}
+
+#define CAMG_NODE_BS_DISPATCH(bs, ...)                                               \
+  switch (bs) {                                                                      \
+    case 1: { constexpr int BS = 1; __VA_ARGS__; } break;                            \
+    case 2: { constexpr int BS = 2; __VA_ARGS__; } break;                            \
+    case 3: { constexpr int BS = 3; __VA_ARGS__; } break;                            \
+    case 4: { constexpr int BS = 4; __VA_ARGS__; } break;                            \
+    case 5: { constexpr int BS = 5; __VA_ARGS__; } break;                            \
+    case 6: { constexpr int BS = 6; __VA_ARGS__; } break;                            \
+    default: throw std::runtime_error("nodal kernels: node block size must be 1..6"); \
+  }
+
+template <typename T>
+void node_correct(const DCSR<T>& G, const int32_t* nodes, int n_list, const T* delta, const T* M, T scale, T* znu,
+                  int bs, hipStream_t s) {
+  if (n_list <= 0) return;
+  CAMG_NODE_BS_DISPATCH(bs, {
+    k_node_correct<T, BS><<<grid_for(n_list, kBlock / 64), kBlock, 0, s>>>(G, nodes, n_list, delta, M, scale, znu);
+  });
+  CAMG_LAUNCHED();
+}
+
+template <typename T>
+void tcorrect_nodal(const DCSR<T>& BT, const T* su, const T* delta, const T* M, T omega, T a_bt, T c_w, const T* zu,
+                    T* znu, T* t_out, T* w_out, int n_u, int bs, hipStream_t s) {
+  if (n_u <= 0) return;
+  if (bs < 1 || n_u % bs) throw std::runtime_error("tcorrect_nodal: node block size must divide n_u");
+  const int nn = n_u / bs;
+  CAMG_NODE_BS_DISPATCH(bs, {
+    k_tcorrect_nodal<T, BS><<<grid_for(nn, kBlock), kBlock, 0, s>>>(BT, su, delta, M, omega, a_bt, c_w, zu, znu,
+                                                                     t_out, w_out, nn);
+  });
+  CAMG_LAUNCHED();
+}
+#undef CAMG_NODE_BS_DISPATCH
 
 int cgs_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kCgsBlock - 1) / kCgsBlock); }
 
@@ -1458,7 +1612,13 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
                              hipStream_t);                                                                         \
   template T* schur_block_steps<T>(const DCSR<T>&, const T*, T*, T*, const T*, bool, const T*, T, T*, int, int, int, \
                                    hipStream_t);                                                                   \
-  template void node_apply<T>(const T*, const T*, T, const T*, T*, T*, int, int, bool, hipStream_t);               \
+  template void node_apply<T>(const T*, const T*, T, const T*, T*, T*, int, int, bool, hipStream_t, const int32_t*, \
+                              int);                                                                                \
+  template void smooth_u_bell_nodal<T>(const DBELL<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T,  \
+                                       T*, T*, T*, int, hipStream_t);                                              \
+  template void node_correct<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, int, hipStream_t);  \
+  template void tcorrect_nodal<T>(const DCSR<T>&, const T*, const T*, const T*, T, T, T, const T*, T*, T*, T*, int, \
+                                  int, hipStream_t);                                                               \
   template void spmv_axpy<T>(const DCSR<T>&, const T*, T, const T*, T*, int, hipStream_t);                        \
   template void correct_u<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, hipStream_t);         \
   template void tsmooth_u<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, T*, int, bool, int,      \

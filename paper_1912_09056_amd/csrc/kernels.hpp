@@ -74,7 +74,24 @@ T* schur_block_steps(const DCSR<T>& S, const T* q, T* d_a, T* d_b, const T* blk,
 // null, y_in may alias y_out.
 template <typename T>
 void node_apply(const T* M, const T* x, T scale, const T* y_in, T* y_out, T* w_out, int n, int bs, bool trans,
-                hipStream_t s);
+                hipStream_t s, const int32_t* list = nullptr, int n_list = 0);
+
+// Nodal lumping option on the level-0 blocked-ELL layout: t = b_u - K z_u -
+// G z_l, w = omega M t per node, zn_u = z_u + w (t_out, w_out optional).
+template <typename T>
+void smooth_u_bell_nodal(const DBELL<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* M,
+                         T omega, T* znu, T* t_out, T* w_out, int n_u, hipStream_t s);
+
+// Nodal lumping option: zn_u += scale * M (G delta) on the listed nodes.
+template <typename T>
+void node_correct(const DCSR<T>& G, const int32_t* nodes, int n_list, const T* delta, const T* M, T scale, T* znu,
+                  int bs, hipStream_t s);
+
+// Nodal lumping option, adjoint: t = s_u - a_bt B^T delta, w = omega M^T t,
+// zn_u = z_u + c_w w per node (z_u null: zero; t_out, w_out optional).
+template <typename T>
+void tcorrect_nodal(const DCSR<T>& BT, const T* su, const T* delta, const T* M, T omega, T a_bt, T c_w, const T* zu,
+                    T* znu, T* t_out, T* w_out, int n_u, int bs, hipStream_t s);
 
 // y = b - a * (A x) over A's n rows (b null: zero).
 template <typename T>

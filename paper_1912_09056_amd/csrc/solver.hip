@@ -198,6 +198,8 @@ struct DevLevel {
   int sg_S = 8;
   int sblk_bs = 0;     // > 0: the Schur step relaxes with nodal blocks of this size
   int ablk_bs = 0;     // > 0: nodal lumping blocks of this size (the nodal sweep)
+  DBuf<int32_t> g_nodes;  // nodal sweep: nodes with a nonempty G row (the back-substitution's support)
+  int32_t n_g_nodes = 0;
   bool bell = false;   // K and K^T in sliced blocked-ELL layout
   DevBell Kb, KTb;
   int64_t k_blocks = 0, k_slots = 0;
@@ -440,6 +442,19 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
     }
     D.sblk_bs = (!dense_coarse && !H.sblk_inv.empty()) ? H.bs_l : 0;
     D.ablk_bs = (!dense_coarse && !H.ablk_inv.empty()) ? H.bs_u : 0;
+    if (D.ablk_bs > 0) {
+      std::vector<int32_t> gn;
+      for (int64_t nd = 0; nd < H.n_u() / H.bs_u; ++nd) {
+        bool any = false;
+        for (int b = 0; b < H.bs_u; ++b) {
+          const int64_t i = nd * H.bs_u + b;
+          any = any || H.G.rp[i + 1] > H.G.rp[i];
+        }
+        if (any) gn.push_back((int32_t)nd);
+      }
+      D.n_g_nodes = (int32_t)gn.size();
+      D.g_nodes.upload(gn, s);
+    }
     if (mixed) alloc_vecs<float>(D.v32, H, dense_coarse, s);
     else alloc_vecs<double>(D.v64, H, dense_coarse, s);
     if (mixed && l == 0) {
@@ -493,8 +508,6 @@ static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const 
   const bool sblock = D.sblk_bs > 0;
   T* q = V.qrhs.p;
   const T* sdv = sblock ? nullptr : V.sdinv.p;
-  // the V-cycle passes its own work buffer as z; from zero it is cleared
-  if (first) zero_vec<T>(const_cast<T*>(z), D.n(), s);
   const T* bu = b;
   const T* bl = b + nu;
   const T* zu = z;
@@ -505,53 +518,87 @@ static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const 
   DCSR<T> none;
   // delta from q = -(r_l - B w): the multiplier kernel already divided by the
   // diagonal (point options) or only stored q (nodal Schur blocks)
-  auto schur = [&](const DevMat& SM, bool trans) -> const T* {
+  auto schur = [&](const DevMat& SM, const T* zl_in, bool trans) -> const T* {
     if (sblock)
-      return schur_block_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sblk.p, trans, zl, al, znl, ks + 1, nl,
-                                  D.sblk_bs, s);
-    return schur_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, zl, al, znl, ks, nl, D.sg_S, s);
+      return schur_block_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sblk.p, trans, zl_in, al, znl, ks + 1,
+                                  nl, D.sblk_bs, s);
+    return schur_steps<T>(SM.view<T>(), q, V.delta.p, V.delta2.p, V.sdinv.p, zl_in, al, znl, ks, nl, D.sg_S, s);
   };
   T* wa = V.aux2.p;
   T* wb = V.su.p;
   T* tr = V.r.p;  // r is free during a sweep
   if (!transpose) {
-    T* t = V.aux1.p;
-    blk_spmv<T>(D.K.view<T>(), D.G.view<T>(), none, none, zu, zl, bu, nullptr, t, nullptr, nu, 0, 1, D.sg_K, s);
-    node_apply<T>(M, t, om, nullptr, nullptr, wa, nu, bs, false, s);
+    // prediction: t = b_u - K z_u - G z_l (t = b_u from zero), w = J(t), zn_u = z_u + w
+    const T* t = bu;
+    bool zn_done = false;
+    if (!first && D.bell) {
+      smooth_u_bell_nodal<T>(D.Kb.view<T>(), D.G.view<T>(), zu, zl, bu, M, om, znu, nj > 1 ? V.aux1.p : nullptr, wa,
+                             nu, s);
+      t = V.aux1.p;
+      zn_done = nj == 1;
+    } else {
+      if (!first) {
+        blk_spmv<T>(D.K.view<T>(), D.G.view<T>(), none, none, zu, zl, bu, nullptr, V.aux1.p, nullptr, nu, 0, 1,
+                    D.sg_K, s);
+        t = V.aux1.p;
+      }
+      node_apply<T>(M, t, om, nullptr, nullptr, wa, nu, bs, false, s);
+    }
     for (int k = 1; k < nj; ++k) {
-      blk_spmv<T>(D.K.view<T>(), none, none, none, wa, nullptr, t, nullptr, tr, nullptr, nu, 0, 1, D.sg_K, s);
+      if (D.bell)
+        blk_spmv_bell<T>(D.Kb.view<T>(), none, none, none, wa, nullptr, t, nullptr, tr, nullptr, nu, 0, 1, s);
+      else
+        blk_spmv<T>(D.K.view<T>(), none, none, none, wa, nullptr, t, nullptr, tr, nullptr, nu, 0, 1, D.sg_K, s);
       node_apply<T>(M, tr, om, wa, wb, nullptr, nu, bs, false, s);
       std::swap(wa, wb);
     }
-    uzawa_update<T>(zu, wa, T(1), znu, nu, s);  // zn_u = z_u + w
-    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, sdv, al, znl, V.delta.p, q, nl, false, s);
-    const T* dfin = schur(D.S, false);
-    if (uzawa) {
-      uzawa_update<T>(zu, wa, al, znu, nu, s);
-    } else {
-      spmv_axpy<T>(D.G.view<T>(), dfin, T(-1), nullptr, tr, nu, s);  // G delta
-      node_apply<T>(M, tr, -al, znu, znu, nullptr, nu, bs, false, s);
-    }
+    if (!zn_done) uzawa_update<T>(first ? nullptr : zu, wa, T(1), znu, nu, s);
+    smooth_l<T>(D.B.view<T>(), D.C.view<T>(), znu, zl, bl, sdv, al, znl, V.delta.p, q, nl, first, s);
+    const T* dfin = schur(D.S, first ? nullptr : zl, false);
+    if (uzawa)
+      uzawa_update<T>(first ? nullptr : zu, wa, al, znu, nu, s);
+    else  // back-substitution on the interface nodes: zn_u -= alpha M G delta
+      node_correct<T>(D.G.view<T>(), D.g_nodes.p, D.n_g_nodes, dfin, M, -al, znu, bs, s);
   } else {
-    T* su = V.aux1.p;
-    tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, su, nu, false, D.sg_K, s);
-    const T* y = zu;
+    // from zero only the multiplier part of z is read (cleared here)
+    if (first) zero_vec<T>(const_cast<T*>(zl), nl, s);
+    const T* su = bu;
+    if (!first) {
+      if (D.bell)
+        tsmooth_u_bell<T>(D.KTb.view<T>(), D.BT.view<T>(), zu, zl, bu, V.aux1.p, nu, s);
+      else
+        tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.aux1.p, nu, false, D.sg_K, s);
+      su = V.aux1.p;
+    }
+    // q = -(s_l - G^T M^T s_u) = -(b_l - G^T (z_u + M^T s_u) - C^T z_l); G^T reads
+    // its argument only on the interface nodes
+    const T* y = first ? nullptr : zu;
     if (!uzawa) {
-      node_apply<T>(M, su, T(1), zu, tr, nullptr, nu, bs, true, s);  // z_u + M^T s_u
+      node_apply<T>(M, su, T(1), first ? nullptr : zu, tr, nullptr, nu, bs, true, s, D.g_nodes.p, D.n_g_nodes);
       y = tr;
     }
-    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), y, zl, bl, su, nullptr, sdv, al, znl, V.delta.p, q, nl, false, s);
-    const T* dfin = schur(D.ST, true);
-    T* t = tr;
-    spmv_axpy<T>(D.BT.view<T>(), dfin, uzawa ? T(1) : al, su, t, nu, s);  // s_u - a B^T delta
-    node_apply<T>(M, t, om, nullptr, nullptr, wa, nu, bs, true, s);
-    T* tk = su;  // s_u is no longer needed
-    for (int k = 1; k < nj; ++k) {
-      blk_spmv<T>(D.KT.view<T>(), none, none, none, wa, nullptr, t, nullptr, tk, nullptr, nu, 0, 1, D.sg_K, s);
-      node_apply<T>(M, tk, om, wa, wb, nullptr, nu, bs, true, s);
-      std::swap(wa, wb);
+    tsmooth_l<T>(D.GT.view<T>(), D.CT.view<T>(), y, zl, bl, su, nullptr, sdv, al, znl, V.delta.p, q, nl, y == nullptr,
+                 s);
+    const T* dfin = schur(D.ST, zl, true);
+    // zn_u = z_u + c J^T(s_u - a B^T delta) with M^T
+    const T a_bt = uzawa ? T(1) : al;
+    const T c_w = uzawa ? al : T(1);
+    T* t = V.r.p;
+    tcorrect_nodal<T>(D.BT.view<T>(), su, dfin, M, om, a_bt, c_w, first ? nullptr : zu, znu, nj > 1 ? t : nullptr,
+                      nj > 1 ? wa : nullptr, nu, bs, s);
+    if (nj > 1) {
+      T* tk = V.aux1.p == su ? V.su.p : V.aux1.p;  // s_u is no longer needed
+      wb = (tk == V.su.p) ? V.aux1.p : V.su.p;
+      for (int k = 1; k < nj; ++k) {
+        if (D.bell)
+          blk_spmv_bell<T>(D.KTb.view<T>(), none, none, none, wa, nullptr, t, nullptr, tk, nullptr, nu, 0, 1, s);
+        else
+          blk_spmv<T>(D.KT.view<T>(), none, none, none, wa, nullptr, t, nullptr, tk, nullptr, nu, 0, 1, D.sg_K, s);
+        node_apply<T>(M, tk, om, wa, wb, nullptr, nu, bs, true, s);
+        std::swap(wa, wb);
+      }
+      uzawa_update<T>(first ? nullptr : zu, wa, c_w, znu, nu, s);
     }
-    uzawa_update<T>(zu, wa, uzawa ? al : T(1), znu, nu, s);
   }
 }
 
