@@ -667,6 +667,18 @@ __device__ __forceinline__ T bell_row(const DBELL<T>& A, const T* __restrict__ x
 
 // Row of a BELL matrix times a vector of another precision (converted on
 // load).
+// XCD-aware slice order for the blocked-ELL kernels: the dispatcher hands
+// consecutive workgroups to the 8 XCDs in turn, so workgroup g runs on XCD
+// g % 8.  Mapping g to slice start(g % 8) + g / 8 gives each XCD one
+// contiguous range of slices (nodes), and the x-gathers of neighbouring
+// slices hit that XCD's own L2 instead of being fetched once per XCD.  A
+// bijection on [0, n): XCD x owns n / 8 slices, plus one when x < n % 8.
+__device__ __forceinline__ int xcd_slice(int g, int n) {
+  constexpr int kXcd = 8;
+  const int x = g % kXcd, q = n / kXcd, rem = n % kXcd;
+  return x * q + min(x, rem) + g / kXcd;
+}
+
 template <typename T, typename XT, int BS>
 __device__ __forceinline__ T bell_row_x(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
   const int bs = BS > 0 ? BS : A.bs;
@@ -697,7 +709,7 @@ __global__ void k_blk_spmv_bell(DBELL<T> K, DCSR<T> A12, DCSR<T> A21, DCSR<T> A2
   const int bs = BS > 0 ? BS : K.bs;
   if ((int)blockIdx.x < K.n_slices) {
     const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
-    const int slice = blockIdx.x;
+    const int slice = xcd_slice((int)blockIdx.x, K.n_slices);
     T s = bell_row_x<T, XT, BS>(K, x1, slice, lane, a);
     const int node = slice * 64 + lane;
     if (node >= K.n_nodes) return;
@@ -726,7 +738,7 @@ __global__ void k_smooth_u_bell(DBELL<T> K, DCSR<T> G, const T* __restrict__ zu,
                                 T* __restrict__ r_out, T* __restrict__ w_out) {
   const int bs = BS > 0 ? BS : K.bs;
   const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
-  const int slice = blockIdx.x;
+  const int slice = xcd_slice((int)blockIdx.x, (int)gridDim.x);
   T s = bell_row<T, BS>(K, zu, slice, lane, a);
   const int node = slice * 64 + lane;
   if (node >= K.n_nodes) return;
@@ -746,7 +758,7 @@ __global__ void k_tsmooth_u_bell(DBELL<T> KT, DCSR<T> BT, const T* __restrict__ 
                                  const T* __restrict__ bu, T* __restrict__ su) {
   const int bs = BS > 0 ? BS : KT.bs;
   const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
-  const int slice = blockIdx.x;
+  const int slice = xcd_slice((int)blockIdx.x, (int)gridDim.x);
   T s = bell_row<T, BS>(KT, zu, slice, lane, a);
   const int node = slice * 64 + lane;
   if (node >= KT.n_nodes) return;
@@ -761,7 +773,7 @@ __global__ void k_jacobi_extra_bell(DBELL<T> M, const T* __restrict__ w, const T
                                     const T* __restrict__ zu, T* __restrict__ znu, int last) {
   const int bs = BS > 0 ? BS : M.bs;
   const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
-  const int slice = blockIdx.x;
+  const int slice = xcd_slice((int)blockIdx.x, (int)gridDim.x);
   T s = bell_row<T, BS>(M, w, slice, lane, a);
   const int node = slice * 64 + lane;
   if (node >= M.n_nodes) return;
@@ -783,7 +795,7 @@ __global__ void k_smooth_u_bell_nodal(DBELL<T> K, DCSR<T> G, const T* __restrict
                                       T* __restrict__ znu, T* __restrict__ t_out, T* __restrict__ w_out) {
   __shared__ T tl[BS][64];
   const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
-  const int slice = blockIdx.x;
+  const int slice = xcd_slice((int)blockIdx.x, (int)gridDim.x);
   T s = bell_row<T, BS>(K, zu, slice, lane, a);
   const int node = slice * 64 + lane;
   const bool live = node < K.n_nodes;
