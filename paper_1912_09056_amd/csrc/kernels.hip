@@ -885,6 +885,76 @@ __global__ void __launch_bounds__(kBlock) k_tcorrect_nodal(DCSR<T> BT, const T* 
   }
 }
 
+// Aggregation transfers with the tentative pattern (plain aggregation): fine
+// row i holds exactly its aggregate's NS coarse columns base[i] ..
+// base[i] + NS - 1 (base -1: a zeroed row), its values dense per row, so no
+// column indices are stored.  Prolongation y += P x, one thread per fine row
+// (displacement rows, then multiplier rows).
+template <typename T, int NSU, int NSL>
+__global__ void __launch_bounds__(kBlock) k_prolong_agg(const int32_t* __restrict__ base_u, const T* __restrict__ pu,
+                                                        const int32_t* __restrict__ base_l, const T* __restrict__ pl,
+                                                        const T* __restrict__ xu, const T* __restrict__ xl,
+                                                        T* __restrict__ yu, T* __restrict__ yl, int nu, int nl) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nu) {
+    const int c = base_u[i];
+    if (c < 0) return;
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < NSU; ++k) s += pu[(size_t)i * NSU + k] * xu[c + k];
+    yu[i] += s;
+  } else if (i < nu + nl) {
+    const int j = i - nu;
+    const int c = base_l[j];
+    if (c < 0) return;
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < NSL; ++k) s += pl[(size_t)j * NSL + k] * xl[c + k];
+    yl[j] += s;
+  }
+}
+
+// Restriction y = P^T r with the same storage, one SG-lane subgroup per
+// aggregate: its fine rows (ascending, from the aggregate's row list) are
+// read once and the NS coarse sums accumulate together.
+template <typename T, int NS, int SG>
+__device__ __forceinline__ void restrict_one(const int32_t* __restrict__ ptr, const int32_t* __restrict__ rows,
+                                             const T* __restrict__ pv, const T* __restrict__ r, T* __restrict__ y,
+                                             int a, int lane) {
+  T acc[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = T(0);
+  const int e = ptr[a + 1];
+  for (int p = ptr[a] + lane; p < e; p += SG) {
+    const int i = rows[p];
+    const T ri = r[i];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) acc[k] += pv[(size_t)i * NS + k] * ri;
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const T t = sg_reduce<T, SG>(acc[k]);
+    if (lane == k) y[(size_t)a * NS + k] = t;
+  }
+}
+
+template <typename T, int NSU, int NSL, int SG>
+__global__ void __launch_bounds__(kBlock) k_restrict_agg(const int32_t* __restrict__ ptr_u,
+                                                         const int32_t* __restrict__ rows_u, const T* __restrict__ pu,
+                                                         const int32_t* __restrict__ ptr_l,
+                                                         const int32_t* __restrict__ rows_l, const T* __restrict__ pl,
+                                                         const T* __restrict__ ru, const T* __restrict__ rl,
+                                                         T* __restrict__ yu, T* __restrict__ yl, int n_agg_u,
+                                                         int n_agg_l) {
+  static_assert(NSU <= SG && NSL <= SG, "one lane per coarse row of an aggregate");
+  const int a = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
+  const int lane = threadIdx.x % SG;
+  if (a < n_agg_u)
+    restrict_one<T, NSU, SG>(ptr_u, rows_u, pu, ru, yu, a, lane);
+  else if (a < n_agg_u + n_agg_l)
+    restrict_one<T, NSL, SG>(ptr_l, rows_l, pl, rl, yl, a - n_agg_u, lane);
+}
+
 // ---- Krylov -----------------------------------------------------------------
 
 constexpr int kDotGroup = 8;
@@ -1480,6 +1550,37 @@ void tcorrect_nodal(const DCSR<T>& BT, const T* su, const T* delta, const T* M, 
 }
 #undef CAMG_NODE_BS_DISPATCH
 
+template <typename T>
+bool agg_transfer(const AggTransferView<T>& t, bool restrict_dir, const T* xu, const T* xl, T* yu, T* yl,
+                  hipStream_t s) {
+  const int nfine = t.n_u + t.n_l;
+  if (restrict_dir) {
+    constexpr int SG = 64;  // one wave per aggregate (enough loads in flight per aggregate)
+    const int na = t.n_agg_u + t.n_agg_l;
+    if (na <= 0) return true;
+    const unsigned g = grid_for(na, kBlock / SG);
+    if (t.ns_u == 6 && t.ns_l == 3)
+      k_restrict_agg<T, 6, 3, SG><<<g, kBlock, 0, s>>>(t.ptr_u, t.rows_u, t.pu, t.ptr_l, t.rows_l, t.pl, xu, xl, yu, yl,
+                                                       t.n_agg_u, t.n_agg_l);
+    else if (t.ns_u == 3 && t.ns_l == 2)
+      k_restrict_agg<T, 3, 2, SG><<<g, kBlock, 0, s>>>(t.ptr_u, t.rows_u, t.pu, t.ptr_l, t.rows_l, t.pl, xu, xl, yu, yl,
+                                                       t.n_agg_u, t.n_agg_l);
+    else
+      return false;
+  } else {
+    if (nfine <= 0) return true;
+    const unsigned g = grid_for(nfine, kBlock);
+    if (t.ns_u == 6 && t.ns_l == 3)
+      k_prolong_agg<T, 6, 3><<<g, kBlock, 0, s>>>(t.base_u, t.pu, t.base_l, t.pl, xu, xl, yu, yl, t.n_u, t.n_l);
+    else if (t.ns_u == 3 && t.ns_l == 2)
+      k_prolong_agg<T, 3, 2><<<g, kBlock, 0, s>>>(t.base_u, t.pu, t.base_l, t.pl, xu, xl, yu, yl, t.n_u, t.n_l);
+    else
+      return false;
+  }
+  CAMG_LAUNCHED();
+  return true;
+}
+
 int cgs_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kCgsBlock - 1) / kCgsBlock); }
 
 #define CAMG_KMAX_DISPATCH(kk, ...)  \
@@ -1628,6 +1729,7 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
                               int);                                                                                \
   template void smooth_u_bell_nodal<T>(const DBELL<T>&, const DCSR<T>&, const T*, const T*, const T*, const T*, T,  \
                                        T*, T*, T*, int, hipStream_t);                                              \
+  template bool agg_transfer<T>(const AggTransferView<T>&, bool, const T*, const T*, T*, T*, hipStream_t);          \
   template void node_correct<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, int, hipStream_t);  \
   template void tcorrect_nodal<T>(const DCSR<T>&, const T*, const T*, const T*, T, T, T, const T*, T*, T*, T*, int, \
                                   int, hipStream_t);                                                               \

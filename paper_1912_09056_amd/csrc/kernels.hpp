@@ -82,6 +82,25 @@ template <typename T>
 void smooth_u_bell_nodal(const DBELL<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* M,
                          T omega, T* znu, T* t_out, T* w_out, int n_u, hipStream_t s);
 
+// Aggregation transfers with the tentative pattern (no column indices):
+// fine row i couples to coarse columns base[i] .. base[i] + ns - 1 (base -1:
+// none) with dense per-row values pv[i * ns + k]; ptr/rows list each
+// aggregate's fine rows (ascending) for the restriction.
+template <typename T>
+struct AggTransferView {
+  int n_u = 0, n_l = 0, ns_u = 0, ns_l = 0, n_agg_u = 0, n_agg_l = 0;
+  const int32_t *base_u = nullptr, *base_l = nullptr;
+  const int32_t *ptr_u = nullptr, *rows_u = nullptr, *ptr_l = nullptr, *rows_l = nullptr;
+  const T *pu = nullptr, *pl = nullptr;
+};
+
+// Restriction (restrict_dir: y = P^T x, coarse y) or prolongation (y += P x,
+// fine y) for both blocks in one launch; false when the null-space sizes
+// have no instantiation (the caller then uses the CSR transfers).
+template <typename T>
+bool agg_transfer(const AggTransferView<T>& t, bool restrict_dir, const T* xu, const T* xl, T* yu, T* yl,
+                  hipStream_t s);
+
 // Nodal lumping option: zn_u += scale * M (G delta) on the listed nodes.
 template <typename T>
 void node_correct(const DCSR<T>& G, const int32_t* nodes, int n_list, const T* delta, const T* M, T scale, T* znu,

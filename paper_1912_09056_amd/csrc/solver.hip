@@ -206,10 +206,68 @@ struct DevLevel {
   DBuf<int32_t> g_rows;
   int32_t n_g_rows = 0;
   int sg_K = 16, sg_R = 16, sg_P = 8;
+  // transfers with the tentative aggregate pattern stored without column
+  // indices (agg_ok); otherwise the CSR P / R above
+  bool agg_ok = false;
+  int ns_u = 0, ns_l = 0, n_agg_u = 0, n_agg_l = 0;
+  DBuf<int32_t> base_u, base_l, aptr_u, arows_u, aptr_l, arows_l;
+  DBuf<double> pu64, pl64;
+  DBuf<float> pu32, pl32;
+  template <typename T>
+  AggTransferView<T> agg_view() const;
   LevelVecs<double> v64;
   LevelVecs<float> v32;
   int64_t n() const { return n_u + n_l; }
 };
+
+template <>
+AggTransferView<double> DevLevel::agg_view<double>() const {
+  AggTransferView<double> t;
+  t.n_u = (int)n_u, t.n_l = (int)n_l, t.ns_u = ns_u, t.ns_l = ns_l, t.n_agg_u = n_agg_u, t.n_agg_l = n_agg_l;
+  t.base_u = base_u.p, t.base_l = base_l.p, t.ptr_u = aptr_u.p, t.rows_u = arows_u.p, t.ptr_l = aptr_l.p;
+  t.rows_l = arows_l.p, t.pu = pu64.p, t.pl = pl64.p;
+  return t;
+}
+template <>
+AggTransferView<float> DevLevel::agg_view<float>() const {
+  AggTransferView<float> t;
+  t.n_u = (int)n_u, t.n_l = (int)n_l, t.ns_u = ns_u, t.ns_l = ns_l, t.n_agg_u = n_agg_u, t.n_agg_l = n_agg_l;
+  t.base_u = base_u.p, t.base_l = base_l.p, t.ptr_u = aptr_u.p, t.rows_u = arows_u.p, t.ptr_l = aptr_l.p;
+  t.rows_l = arows_l.p, t.pu = pu32.p, t.pl = pl32.p;
+  return t;
+}
+
+// Whether P has the tentative aggregate pattern: every row empty or exactly
+// the ns consecutive columns of one aggregate (first column a multiple of
+// ns).  Fills the per-row base column (-1 for empty rows), dense per-row
+// values and each aggregate's ascending fine-row list.
+static bool agg_pattern(const HostCSR& P, int ns, std::vector<int32_t>& base, std::vector<double>& vals,
+                        std::vector<int32_t>& aptr, std::vector<int32_t>& arows) {
+  if (ns <= 0 || P.ncols % ns) return false;
+  const int64_t n = P.nrows, n_agg = P.ncols / ns;
+  base.assign((size_t)n, -1);
+  vals.assign((size_t)(n * ns), 0.0);
+  aptr.assign((size_t)n_agg + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t r0 = P.rp[i], len = P.rp[i + 1] - r0;
+    if (len == 0) continue;
+    if (len != ns) return false;
+    const int32_t c0 = P.ci[r0];
+    if (c0 % ns) return false;
+    for (int k = 0; k < ns; ++k) {
+      if (P.ci[r0 + k] != c0 + k) return false;
+      vals[(size_t)(i * ns + k)] = P.v[r0 + k];
+    }
+    base[(size_t)i] = c0;
+    ++aptr[(size_t)(c0 / ns) + 1];
+  }
+  for (int64_t a = 0; a < n_agg; ++a) aptr[(size_t)a + 1] += aptr[(size_t)a];
+  arows.assign((size_t)aptr.back(), 0);
+  std::vector<int32_t> fill(aptr.begin(), aptr.end() - 1);
+  for (int64_t i = 0; i < n; ++i)
+    if (base[(size_t)i] >= 0) arows[(size_t)fill[(size_t)(base[(size_t)i] / ns)]++] = (int32_t)i;
+  return true;
+}
 
 // ---------------------------------------------------------------------------
 // profiling (hipEvents around launches of selected kernel classes)
@@ -425,6 +483,29 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       upload_mat(D.Rl, Rl, t64, f32, s);
       D.sg_R = pick_subgroup(Ru.nnz(), Ru.nrows);
       D.sg_P = pick_subgroup(H.P_u.nnz(), H.P_u.nrows);
+      std::vector<int32_t> bu, bl, pu_, ru_, pl_, rl_;
+      std::vector<double> vu, vl;
+      D.agg_ok = agg_pattern(H.P_u, H.n_ns_u, bu, vu, pu_, ru_) && agg_pattern(H.P_l, H.n_ns_l, bl, vl, pl_, rl_) &&
+                 ((H.n_ns_u == 6 && H.n_ns_l == 3) || (H.n_ns_u == 3 && H.n_ns_l == 2));
+      if (D.agg_ok) {
+        D.ns_u = H.n_ns_u, D.ns_l = H.n_ns_l;
+        D.n_agg_u = (int)(pu_.size() - 1), D.n_agg_l = (int)(pl_.size() - 1);
+        D.base_u.upload(bu, s);
+        D.base_l.upload(bl, s);
+        D.aptr_u.upload(pu_, s);
+        D.arows_u.upload(ru_, s);
+        D.aptr_l.upload(pl_, s);
+        D.arows_l.upload(rl_, s);
+        if (t64) {
+          D.pu64.upload(vu, s);
+          D.pl64.upload(vl, s);
+        } else {
+          std::vector<float> fu(vu.begin(), vu.end()), fl(vl.begin(), vl.end());
+          D.pu32.upload(fu, s);
+          D.pl32.upload(fl, s);
+        }
+        CAMG_HIP(hipStreamSynchronize(s));
+      }
     }
     const bool dense_coarse = coarsest && h.opts.coarse_solver == CAMG_COARSE_LU;
     if (!dense_coarse) {
@@ -759,11 +840,13 @@ static T* vcycle_level(amg_handle& h, int l, bool transpose, hipStream_t s) {
   LevelVecs<T>& Vc = vecs<T>(Dc);
   const int ncu = (int)Dc.n_u, ncl = (int)Dc.n_l;
   DCSR<T> none;
-  blk_spmv<T>(D.Ru.view<T>(), none, none, D.Rl.view<T>(), V.r.p, V.r.p + nu, nullptr, nullptr, Vc.b.p, Vc.b.p + ncu,
-              ncu, ncl, 0, D.sg_R, s);
+  if (!(D.agg_ok && agg_transfer<T>(D.agg_view<T>(), true, V.r.p, V.r.p + nu, Vc.b.p, Vc.b.p + ncu, s)))
+    blk_spmv<T>(D.Ru.view<T>(), none, none, D.Rl.view<T>(), V.r.p, V.r.p + nu, nullptr, nullptr, Vc.b.p,
+                Vc.b.p + ncu, ncu, ncl, 0, D.sg_R, s);
   T* zcoarse = vcycle_level<T>(h, l + 1, transpose, s);
-  blk_spmv<T>(D.Pu.view<T>(), none, none, D.Pl.view<T>(), zcoarse, zcoarse + ncu, nullptr, nullptr, zc, zc + nu, nu,
-              nl, 2, D.sg_P, s);
+  if (!(D.agg_ok && agg_transfer<T>(D.agg_view<T>(), false, zcoarse, zcoarse + ncu, zc, zc + nu, s)))
+    blk_spmv<T>(D.Pu.view<T>(), none, none, D.Pl.view<T>(), zcoarse, zcoarse + ncu, nullptr, nullptr, zc, zc + nu,
+                nu, nl, 2, D.sg_P, s);
   for (int k = 0; k < npost; ++k) {
     sweep<T>(h, l, transpose, V.b.p, zc, zx, false, s);
     std::swap(zc, zx);
