@@ -84,6 +84,14 @@ struct DCSR {
   const int32_t* rp = nullptr;
   const int32_t* ci = nullptr;
   const T* v = nullptr;
+  // Optional node-blocked copy of the same matrix (bs > 0): the bs rows of a
+  // node share block columns bcol[bptr[node] .. bptr[node+1]) and block p
+  // holds its values row-major at bval[p bs^2 ...]; the row dots use it when
+  // present (one column index per bs^2 values instead of one per value).
+  int32_t bs = 0;
+  const int32_t* bptr = nullptr;
+  const int32_t* bcol = nullptr;
+  const T* bval = nullptr;
 };
 
 // Device sliced blocked-ELL view of a square node-blocked matrix (bs x bs

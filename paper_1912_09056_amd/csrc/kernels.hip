@@ -40,8 +40,26 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return t;  // valid in thread 0
 }
 
+// Row dot over the node-blocked copy (A.bs > 0): lane-strided over the
+// node's blocks, each block's bs values of this row against bs consecutive x.
+template <typename T, int SG, int BS>
+__device__ __forceinline__ T block_row_dot(const DCSR<T>& A, const T* __restrict__ x, int row, int lane) {
+  const int node = row / BS, a = row % BS;
+  const int e = A.bptr[node + 1];
+  T s = T(0);
+  for (int p = A.bptr[node] + lane; p < e; p += SG) {
+    const T* __restrict__ v = A.bval + ((size_t)p * BS + a) * BS;
+    const T* __restrict__ xc = x + (size_t)A.bcol[p] * BS;
+#pragma unroll
+    for (int b = 0; b < BS; ++b) s += v[b] * xc[b];
+  }
+  return s;
+}
+
 template <typename T, int SG>
 __device__ __forceinline__ T row_dot(const DCSR<T>& A, const T* __restrict__ x, int row, int lane) {
+  if (A.bs == 6) return block_row_dot<T, SG, 6>(A, x, row, lane);
+  if (A.bs == 3) return block_row_dot<T, SG, 3>(A, x, row, lane);
   T s = T(0);
   const int e = A.rp[row + 1];
 #pragma unroll 4
@@ -73,6 +91,16 @@ __device__ __forceinline__ void row_dot2(const DCSR<T>& A, const T* __restrict__
 // of 2 per chunk instead of 2 per entry.
 template <typename T, typename XT>
 __device__ __forceinline__ T csr_row_serial_x(const DCSR<T>& A, const XT* __restrict__ x, int row) {
+  if (A.bs > 0) {  // node-blocked copy: one thread walks the row's blocks
+    const int bs = A.bs, node = row / bs, a = row % bs;
+    T s = T(0);
+    for (int p = A.bptr[node]; p < A.bptr[node + 1]; ++p) {
+      const T* v = A.bval + ((size_t)p * bs + a) * bs;
+      const XT* xc = x + (size_t)A.bcol[p] * bs;
+      for (int b = 0; b < bs; ++b) s += v[b] * (T)xc[b];
+    }
+    return s;
+  }
   constexpr int U = 8;
   const int e = A.rp[row + 1];
   T s = T(0);

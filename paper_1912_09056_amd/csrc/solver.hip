@@ -40,6 +40,10 @@ struct DevMat {
   DBuf<int32_t> rp, ci;
   DBuf<double> v64;
   DBuf<float> v32;
+  int32_t bs = 0;  // > 0: node-blocked copy present (see DCSR)
+  DBuf<int32_t> bptr, bcol;
+  DBuf<double> bv64;
+  DBuf<float> bv32;
   template <typename T>
   DCSR<T> view() const;
 };
@@ -53,6 +57,12 @@ DCSR<double> DevMat::view<double>() const {
   d.rp = rp.p;
   d.ci = ci.p;
   d.v = v64.p;
+  if (bs > 0 && bv64.p) {
+    d.bs = bs;
+    d.bptr = bptr.p;
+    d.bcol = bcol.p;
+    d.bval = bv64.p;
+  }
   return d;
 }
 template <>
@@ -64,6 +74,12 @@ DCSR<float> DevMat::view<float>() const {
   d.rp = rp.p;
   d.ci = ci.p;
   d.v = v32.p;
+  if (bs > 0 && bv32.p) {
+    d.bs = bs;
+    d.bptr = bptr.p;
+    d.bcol = bcol.p;
+    d.bval = bv32.p;
+  }
   return d;
 }
 
@@ -82,6 +98,48 @@ static void upload_mat(DevMat& D, const HostCSR& H, bool f64, bool f32, hipStrea
     D.v32.upload(v32, s);
   }
   CAMG_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
+}
+
+// Node-blocked copy of a CSR matrix whose rows are unions of full bs x bs
+// blocks with the same block columns for all bs rows of a node (the coarse
+// Galerkin blocks K_c = R K P have this shape); false otherwise.
+static bool upload_rowblock(DevMat& D, const HostCSR& H, int bs, bool f64, bool f32, hipStream_t s) {
+  if (bs != 3 && bs != 6) return false;
+  if (H.nrows % bs || H.ncols % bs) return false;
+  const int64_t nn = H.nrows / bs;
+  std::vector<int32_t> bptr((size_t)nn + 1, 0), bcol;
+  std::vector<double> val;
+  for (int64_t nd = 0; nd < nn; ++nd) {
+    const int64_t r0 = nd * bs;
+    const int64_t len = H.rp[r0 + 1] - H.rp[r0];
+    if (len % bs) return false;
+    for (int a = 0; a < bs; ++a) {
+      const int64_t ra = r0 + a;
+      if (H.rp[ra + 1] - H.rp[ra] != len) return false;
+      for (int64_t k = 0; k < len; ++k) {
+        const int32_t c = H.ci[H.rp[ra] + k], c0 = H.ci[H.rp[r0] + k];
+        if (c != c0) return false;
+        if (k % bs == 0 ? c % bs != 0 : c != H.ci[H.rp[ra] + k - 1] + 1) return false;
+      }
+    }
+    const int64_t nb = len / bs;
+    for (int64_t q = 0; q < nb; ++q) {
+      bcol.push_back(H.ci[H.rp[r0] + q * bs] / bs);
+      for (int a = 0; a < bs; ++a)
+        for (int b = 0; b < bs; ++b) val.push_back(H.v[H.rp[r0 + a] + q * bs + b]);
+    }
+    bptr[(size_t)nd + 1] = (int32_t)bcol.size();
+  }
+  D.bs = bs;
+  D.bptr.upload(bptr, s);
+  D.bcol.upload(bcol, s);
+  if (f64) D.bv64.upload(val, s);
+  if (f32) {
+    std::vector<float> v32(val.begin(), val.end());
+    D.bv32.upload(v32, s);
+  }
+  CAMG_HIP(hipStreamSynchronize(s));
+  return true;
 }
 
 // Sliced blocked-ELL copy of a square node-blocked CSR matrix.
@@ -473,6 +531,12 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       } else {
         D.bell = false;
       }
+    }
+    // coarse levels: node-blocked copies of K and K^T for the row dots
+    if (!D.bell && l > 0 && h.opts.spmv_format == CAMG_SPMV_AUTO &&
+        !(coarsest && h.opts.coarse_solver == CAMG_COARSE_LU)) {
+      upload_rowblock(D.K, H.K, H.bs_u, f64, f32, s);
+      upload_rowblock(D.KT, transpose(H.K), H.bs_u, f64, f32, s);
     }
     if (!coarsest) {
       const bool t64 = !mixed;
