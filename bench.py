@@ -73,8 +73,10 @@ def vcycle_matrix_bytes(solver, elem):
     sweep but the first from zero, its extra Jacobi steps, and the residual
     before restriction); G twice per sweep plus the residual; B and C once
     per sweep plus the residual; R and P once.  K in its device layout
-    (3x3 blocks with a 4-byte index, or CSR), the other blocks CSR
-    (value + 4-byte column).  The coarsest level: its dense inverse."""
+    (bs x bs blocks with a 4-byte block index, or CSR), P and R either CSR or
+    index-free (values plus one 4-byte base column per fine row for P, one
+    4-byte row index per fine row for R), the other blocks CSR (value +
+    4-byte column).  The coarsest level: its dense inverse."""
     o = solver.options
     sweeps = o.nu_pre + o.nu_post
     nj = max(1, o.jacobi_sweeps)
@@ -85,7 +87,7 @@ def vcycle_matrix_bytes(solver, elem):
             n = info["n_u"] + info["n_l"]
             total += n * n * elem
             break
-        if info["k_layout"] == 1:
+        if info["k_layout"] in (1, 2):
             kb = info["k_blocks"] * (info["k_bs"] ** 2 * elem + 4)
         else:
             kb = info["nnz_K"] * (elem + 4)
@@ -93,7 +95,11 @@ def vcycle_matrix_bytes(solver, elem):
         total += sweeps * nj * kb
         total += (2 * sweeps + 1) * info["nnz_G"] * e
         total += (sweeps + 1) * (info["nnz_B"] + info["nnz_C"]) * e
-        total += 2 * (solver.level_matrix(l, "P_u").nnz + solver.level_matrix(l, "P_l").nnz) * e
+        nnz_p = solver.level_matrix(l, "P_u").nnz + solver.level_matrix(l, "P_l").nnz
+        if info.get("transfer_layout") == 1:
+            total += 2 * (nnz_p * elem + 4 * (info["n_u"] + info["n_l"]))
+        else:
+            total += 2 * nnz_p * e
     return total
 
 

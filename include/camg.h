@@ -191,10 +191,14 @@ typedef struct {
   int64_t n_nodes_u, n_nodes_l;
   int64_t n_agg_u, n_agg_l; /* aggregates built on this level (0 on the coarsest) */
   double op_complexity;   /* sum over levels of nnz / level-0 nnz (all blocks) */
-  int32_t k_layout;       /* device storage of K: 0 CSR, 1 sliced blocked-ELL (-1: host-only handle) */
+  int32_t k_layout;       /* device storage of K: 0 CSR, 1 sliced blocked-ELL, 2 CSR plus a node-blocked
+                             copy used by the row dots (-1: host-only handle) */
   int32_t k_bs;           /* block size of the blocked layout                */
-  int64_t k_blocks;       /* nonzero bs x bs blocks of K (blocked layout)    */
+  int64_t k_blocks;       /* nonzero bs x bs blocks of K (blocked layouts)   */
   int64_t k_slots;        /* stored blocks including slice padding           */
+  int32_t transfer_layout; /* P and R on device: 0 CSR, 1 tentative aggregate pattern without column
+                              indices (per-row base column, dense row values, per-aggregate row lists);
+                              -1 on the coarsest level or a host-only handle */
 } amg_level_info;
 
 void amg_default_options(amg_options* opts);

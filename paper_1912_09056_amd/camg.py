@@ -121,6 +121,7 @@ class amg_level_info(Structure):
         ("k_bs", c_int32),
         ("k_blocks", c_int64),
         ("k_slots", c_int64),
+        ("transfer_layout", c_int32),
     ]
 
 

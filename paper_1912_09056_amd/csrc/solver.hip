@@ -1390,11 +1390,13 @@ int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out) {
     out->k_bs = L.bs_u;
     out->k_blocks = 0;
     out->k_slots = 0;
+    out->transfer_layout = -1;
     if (!h->lev.empty()) {
       const DevLevel& D = h->lev[level];
-      out->k_layout = D.bell ? 1 : 0;
-      out->k_blocks = D.k_blocks;
+      out->k_layout = D.bell ? 1 : (D.K.bs > 0 ? 2 : 0);
+      out->k_blocks = D.bell ? D.k_blocks : (D.K.bs > 0 ? (int64_t)D.K.bcol.n : 0);
       out->k_slots = D.k_slots;
+      if (level + 1 < (int)h->lev.size()) out->transfer_layout = D.agg_ok ? 1 : 0;
     }
     return CAMG_OK;
   });
