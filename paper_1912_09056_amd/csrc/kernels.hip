@@ -485,18 +485,6 @@ __global__ void __launch_bounds__(kBlock) k_node_apply(const T* __restrict__ M, 
   }
 }
 
-// y = b - a * (A x)   (b null: zero).
-template <typename T, int SG>
-__global__ void __launch_bounds__(kBlock) k_spmv_axpy(DCSR<T> A, const T* __restrict__ x, T a,
-                                                      const T* __restrict__ b, T* __restrict__ y, int n) {
-  const int row = blockIdx.x * (kBlock / SG) + threadIdx.x / SG;
-  const int lane = threadIdx.x % SG;
-  if (row >= n) return;
-  T s = A.nnz ? row_dot<T, SG>(A, x, row, lane) : T(0);
-  s = sg_reduce<T, SG>(s);
-  if (lane == 0) y[row] = (b ? b[row] : T(0)) - a * s;
-}
-
 template <typename T, int SG>
 __global__ void __launch_bounds__(kBlock) k_smooth_u_first_corr(DCSR<T> G, const T* __restrict__ bu,
                                                                 const T* __restrict__ jinv, T omega,
@@ -1082,12 +1070,6 @@ __global__ void __launch_bounds__(kBlock) k_restart_init(const double* __restric
   if (i == 0) out[0] = beta;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scale_by(const double* __restrict__ x, const double* __restrict__ scale,
-                                                     double* __restrict__ y, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) y[i] = x[i] * scale[0];
-}
-
 __global__ void k_hess_solve(const double* __restrict__ H, int ldh, const double* __restrict__ g,
                              double* __restrict__ y, int k) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -1122,12 +1104,6 @@ __global__ void k_scatter_pos64(const double* __restrict__ src, const int64_t* _
                                 double* __restrict__ dst, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e < n) dst[pos[e]] = src[e];
-}
-
-template <typename T>
-__global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, int64_t nnz) {
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e < nnz) dst[e] = (T)src[e];
 }
 
 inline unsigned grid_for(int64_t rows, int rows_per_block) {
@@ -1312,15 +1288,6 @@ void node_apply(const T* M, const T* x, T scale, const T* y_in, T* y_out, T* w_o
     default: CAMG_NODE_APPLY_LAUNCH(6) break;
   }
 #undef CAMG_NODE_APPLY_LAUNCH
-  CAMG_LAUNCHED();
-}
-
-template <typename T>
-void spmv_axpy(const DCSR<T>& A, const T* x, T a, const T* b, T* y, int n, hipStream_t s) {
-  if (n <= 0) return;
-  CAMG_SG_DISPATCH(rows_sg(A.nnz, n), {
-    k_spmv_axpy<T, SG><<<grid_for(n, kBlock / SG), kBlock, 0, s>>>(A, x, a, b, y, n);
-  });
   CAMG_LAUNCHED();
 }
 
@@ -1701,12 +1668,6 @@ void restart_init(const double* r, const double* beta2, double* V0, double* g, i
   CAMG_LAUNCHED();
 }
 
-void scale_by(const double* x, const double* scale, double* y, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  k_scale_by<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, scale, y, n);
-  CAMG_LAUNCHED();
-}
-
 void hess_solve(const double* H, int ldh, const double* g, double* y, int k, hipStream_t s) {
   if (k <= 0) return;
   k_hess_solve<<<1, 64, 0, s>>>(H, ldh, g, y, k);
@@ -1733,13 +1694,6 @@ void scatter_pos64(const double* src, const int64_t* pos, double* dst, int64_t n
   CAMG_LAUNCHED();
 }
 
-template <typename T>
-void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
-  if (nnz <= 0) return;
-  k_convert<T><<<grid_for(nnz, kBlock), kBlock, 0, s>>>(src, dst, nnz);
-  CAMG_LAUNCHED();
-}
-
 #define CAMG_INSTANTIATE(T)                                                                                        \
   template void blk_spmv<T>(const DCSR<T>&, const DCSR<T>&, const DCSR<T>&, const DCSR<T>&, const T*, const T*,   \
                             const T*, const T*, T*, T*, int, int, int, int, hipStream_t);                         \
@@ -1761,7 +1715,6 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
   template void node_correct<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, int, hipStream_t);  \
   template void tcorrect_nodal<T>(const DCSR<T>&, const T*, const T*, const T*, T, T, T, const T*, T*, T*, T*, int, \
                                   int, hipStream_t);                                                               \
-  template void spmv_axpy<T>(const DCSR<T>&, const T*, T, const T*, T*, int, hipStream_t);                        \
   template void correct_u<T>(const DCSR<T>&, const int32_t*, int, const T*, const T*, T, T*, hipStream_t);         \
   template void tsmooth_u<T>(const DCSR<T>&, const DCSR<T>&, const T*, const T*, const T*, T*, int, bool, int,      \
                              hipStream_t);                                                                         \
@@ -1786,7 +1739,6 @@ void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s) {
                                   hipStream_t);                                                                    \
   template void jacobi_extra_bell<T>(const DBELL<T>&, const T*, const T*, const T*, T, T*, const T*, T*, bool, int, \
                                      hipStream_t);                                                                 \
-  template void convert_vals<T>(const double*, T*, int64_t, hipStream_t);                                          \
   template void arnoldi_prep<T>(const double*, const double*, double*, T*, int64_t, hipStream_t);
 
 CAMG_INSTANTIATE(float)

@@ -112,10 +112,6 @@ template <typename T>
 void tcorrect_nodal(const DCSR<T>& BT, const T* su, const T* delta, const T* M, T omega, T a_bt, T c_w, const T* zu,
                     T* znu, T* t_out, T* w_out, int n_u, int bs, hipStream_t s);
 
-// y = b - a * (A x) over A's n rows (b null: zero).
-template <typename T>
-void spmv_axpy(const DCSR<T>& A, const T* x, T a, const T* b, T* y, int n, hipStream_t s);
-
 // zn_u[i] -= alpha * ainv[i] * (G delta)[i] for the listed rows of G.
 template <typename T>
 void correct_u(const DCSR<T>& G, const int32_t* rows, int n_rows, const T* delta, const T* ainv, T alpha, T* znu,
@@ -203,8 +199,6 @@ void arnoldi_update(double* H, int ldh, double* cs, double* sn, double* g, const
 // V0 = r * (1 / sqrt(*beta2)); g = [sqrt(*beta2), 0, ...]; out[0] = sqrt(*beta2)
 void restart_init(const double* r, const double* beta2, double* V0, double* g, int gl, double* out, int64_t n,
                   hipStream_t s);
-// y = x * (*scale)
-void scale_by(const double* x, const double* scale, double* y, int64_t n, hipStream_t s);
 // Back substitution H(0:k,0:k) y = g(0:k).
 void hess_solve(const double* H, int ldh, const double* g, double* y, int k, hipStream_t s);
 
@@ -237,8 +231,5 @@ template <typename T>
 void scatter_perm(const double* src, const int32_t* perm, T* dst, int64_t nnz, hipStream_t s);
 // dst[pos[e]] = src[e] with 64-bit positions (BELL value refresh).
 void scatter_pos64(const double* src, const int64_t* pos, double* dst, int64_t n, hipStream_t s);
-// dst[e] = (T) src[e]
-template <typename T>
-void convert_vals(const double* src, T* dst, int64_t nnz, hipStream_t s);
 
 }  // namespace camg
