@@ -596,7 +596,7 @@ __global__ void __launch_bounds__(kBlock) k_cgs_finish(const double* __restrict_
                                                        const double* __restrict__ h1, const double* __restrict__ h2,
                                                        double* __restrict__ H, int ldh, double* __restrict__ cs,
                                                        double* __restrict__ sn, double* __restrict__ g,
-                                                       double* __restrict__ res) {
+                                                       double* __restrict__ res, double* __restrict__ res_host) {
   __shared__ double lds[kBlock / 64];
   __shared__ double col[65], cl[64], sl[64];
   const int j = kk - 1;
@@ -635,6 +635,11 @@ __global__ void __launch_bounds__(kBlock) k_cgs_finish(const double* __restrict_
     res[0] = fabs(g[j + 1]);
     res[1] = hn;
     res[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (res_host) {  // the host's copy (pinned memory), read after the step's event
+      res_host[0] = res[0];
+      res_host[1] = res[1];
+      res_host[2] = res[2];
+    }
   }
   __syncthreads();
   double* hc = H + (int64_t)j * ldh;
@@ -1029,7 +1034,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_acc(const double* __restrict__ 
 __global__ void k_arnoldi_update(double* __restrict__ H, int ldh, double* __restrict__ cs, double* __restrict__ sn,
                                  double* __restrict__ g, const double* __restrict__ h1,
                                  const double* __restrict__ h2, const double* __restrict__ hn2, int j,
-                                 double* __restrict__ out) {
+                                 double* __restrict__ out, double* __restrict__ out_host) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double* col = H + (int64_t)j * ldh;
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
@@ -1056,6 +1061,11 @@ __global__ void k_arnoldi_update(double* __restrict__ H, int ldh, double* __rest
   out[0] = fabs(g[j + 1]);
   out[1] = hn;
   out[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (out_host) {
+    out_host[0] = out[0];
+    out_host[1] = out[1];
+    out_host[2] = out[2];
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_restart_init(const double* __restrict__ r,
@@ -1616,12 +1626,13 @@ void cgs_pass2(const double* V, int64_t ld, int kk, double* w, int64_t n, const 
 }
 
 void cgs_pass3(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, const double* h2,
-               double* partial, double* H, int ldh, double* cs, double* sn, double* g, double* out, hipStream_t s) {
+               double* partial, double* H, int ldh, double* cs, double* sn, double* g, double* out, double* out_host,
+               hipStream_t s) {
   if (kk < 1 || kk > 64) throw HipError{hipErrorInvalidValue, "cgs_pass3: kk out of range"};
   const int nb = cgs_blocks(n);
   CAMG_KMAX_DISPATCH(kk, { k_cgs<KMAX, 3><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, w, n, h2, partial); });
   CAMG_LAUNCHED();
-  k_cgs_finish<<<1, kBlock, 0, s>>>(partial, nb, kk, h1, h2, H, ldh, cs, sn, g, out);
+  k_cgs_finish<<<1, kBlock, 0, s>>>(partial, nb, kk, h1, h2, H, ldh, cs, sn, g, out, out_host);
   CAMG_LAUNCHED();
 }
 
@@ -1656,8 +1667,8 @@ void gemv_acc(const double* M, int64_t ld, int kk, const double* c, double sign,
 }
 
 void arnoldi_update(double* H, int ldh, double* cs, double* sn, double* g, const double* h1, const double* h2,
-                    const double* hn2, int j, double* out, hipStream_t s) {
-  k_arnoldi_update<<<1, 64, 0, s>>>(H, ldh, cs, sn, g, h1, h2, hn2, j, out);
+                    const double* hn2, int j, double* out, double* out_host, hipStream_t s) {
+  k_arnoldi_update<<<1, 64, 0, s>>>(H, ldh, cs, sn, g, h1, h2, hn2, j, out, out_host);
   CAMG_LAUNCHED();
 }
 

@@ -195,7 +195,7 @@ void gemv_acc(const double* M, int64_t ld, int kk, const double* c, double sign,
 // g.  out[0] = |g[j+1]|, out[1] = H[j+1,j] before rotation, out[2] = 1/out[1]
 // (0 when it vanishes).
 void arnoldi_update(double* H, int ldh, double* cs, double* sn, double* g, const double* h1, const double* h2,
-                    const double* hn2, int j, double* out, hipStream_t s);
+                    const double* hn2, int j, double* out, double* out_host, hipStream_t s);
 // V0 = r * (1 / sqrt(*beta2)); g = [sqrt(*beta2), 0, ...]; out[0] = sqrt(*beta2)
 void restart_init(const double* r, const double* beta2, double* V0, double* g, int gl, double* out, int64_t n,
                   hipStream_t s);
@@ -217,7 +217,8 @@ void cgs_pass1(const double* V, int64_t ld, int kk, const double* w, int64_t n, 
 void cgs_pass2(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, double* partial,
                double* h2, hipStream_t s);
 void cgs_pass3(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, const double* h2,
-               double* partial, double* H, int ldh, double* cs, double* sn, double* g, double* out, hipStream_t s);
+               double* partial, double* H, int ldh, double* cs, double* sn, double* g, double* out, double* out_host,
+               hipStream_t s);
 // v_j of the Arnoldi basis and the V-cycle input: with scale (device
 // scalar, 1/||w||) given, vj = w * scale is written first; then
 // b_out = (T) vj.  Without scale, vj is only read.

@@ -392,6 +392,7 @@ struct amg_handle {
   int m_alloc = 0;
   DBuf<double> V, Z, w, r, H, cs, sn, g, h1, h2, hn2, partial, out, y;
   double* hbuf = nullptr;  // pinned host: [0,4) synchronous reads, then 4 doubles per pipelined slot
+  double* hbuf_dev = nullptr;  // the same memory as a device address (kernels write the slots)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   static constexpr int kSlots = 8;
   hipEvent_t evq[kSlots] = {};
@@ -1076,19 +1077,19 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
           cgs_pass1(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h1.p, s);
           cgs_pass2(h.V.p, n, j + 1, h.w.p, n, h.h1.p, h.partial.p, h.h2.p, s);
           cgs_pass3(h.V.p, n, j + 1, h.w.p, n, h.h1.p, h.h2.p, h.partial.p, h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p,
-                    h.out.p, s);
+                    h.out.p, h.hbuf_dev + 4 + 4 * (j % amg_handle::kSlots), s);
         } else {
           mdot(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h1.p, s);
           gemv_acc(h.V.p, n, j + 1, h.h1.p, -1.0, h.w.p, n, s);
           mdot(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h2.p, s);
           gemv_acc(h.V.p, n, j + 1, h.h2.p, -1.0, h.w.p, n, s);
           mdot(h.w.p, n, 1, h.w.p, n, h.partial.p, h.hn2.p, s);
-          arnoldi_update(h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p, h.h1.p, h.h2.p, h.hn2.p, j, h.out.p, s);
+          arnoldi_update(h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p, h.h1.p, h.h2.p, h.hn2.p, j, h.out.p,
+                         h.hbuf_dev + 4 + 4 * (j % amg_handle::kSlots), s);
         }
       }
-      const int sl = j % amg_handle::kSlots;
-      CAMG_HIP(hipMemcpyAsync(h.hbuf + 4 + 4 * sl, h.out.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-      CAMG_HIP(hipEventRecord(h.evq[sl], s));
+      // the finish kernel wrote the step's result block into pinned slot j % kSlots
+      CAMG_HIP(hipEventRecord(h.evq[j % amg_handle::kSlots], s));
     };
     // Reads step j's result (`lag` steps behind the launches); true = stop.
     auto check = [&](int j) -> bool {
@@ -1348,7 +1349,9 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
     CAMG_HIP(hipGetDevice(&h->device));
     CAMG_HIP(hipEventCreate(&h->ev0));
     CAMG_HIP(hipEventCreate(&h->ev1));
-    CAMG_HIP(hipHostMalloc((void**)&h->hbuf, (4 + 4 * amg_handle::kSlots) * sizeof(double), hipHostMallocDefault));
+    CAMG_HIP(hipHostMalloc((void**)&h->hbuf, (4 + 4 * amg_handle::kSlots) * sizeof(double),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    CAMG_HIP(hipHostGetDevicePointer((void**)&h->hbuf_dev, h->hbuf, 0));
     for (auto& e : h->evq) CAMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     upload_hierarchy(*h, s);
     *out = h.release();
