@@ -666,6 +666,18 @@ __global__ void __launch_bounds__(kBlock) k_arnoldi_prep(const double* __restric
 
 // Row (node 64*slice + lane, component a) of a BELL matrix times x.  BS > 0
 // is the compile-time block size; BS == 0 reads it at run time.
+// A blocked-ELL value, read once per launch.  FP64 values are loaded
+// nontemporally: they are 8/9 of an FP64 pass's bytes, and streaming them
+// past the caches leaves the x-gathers and, in the mixed solve, the FP32
+// level-0 copy of K (152 MB on the 40^3 workload, which fits the 256 MB
+// last-level cache) resident across the FP64 operator applies.  FP32 values
+// load normally (nontemporal was 2 % slower there).
+template <typename T>
+__device__ __forceinline__ T bell_val(const T* p) {
+  if constexpr (sizeof(T) == 8) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 template <typename T, int BS>
 __device__ __forceinline__ T bell_row(const DBELL<T>& A, const T* __restrict__ x, int slice, int lane, int a) {
   const int bs = BS > 0 ? BS : A.bs;
@@ -678,16 +690,14 @@ __device__ __forceinline__ T bell_row(const DBELL<T>& A, const T* __restrict__ x
     const T* __restrict__ xc = x + (int64_t)c * bs;
     if (BS > 0) {
 #pragma unroll
-      for (int b = 0; b < BS; ++b) acc += v[b * 64] * xc[b];
+      for (int b = 0; b < BS; ++b) acc += bell_val(v + b * 64) * xc[b];
     } else {
-      for (int b = 0; b < bs; ++b) acc += v[b * 64] * xc[b];
+      for (int b = 0; b < bs; ++b) acc += bell_val(v + b * 64) * xc[b];
     }
   }
   return acc;
 }
 
-// Row of a BELL matrix times a vector of another precision (converted on
-// load).
 // XCD-aware slice order for the blocked-ELL kernels: the dispatcher hands
 // consecutive workgroups to the 8 XCDs in turn, so workgroup g runs on XCD
 // g % 8.  Mapping g to slice start(g % 8) + g / 8 gives each XCD one
@@ -700,6 +710,8 @@ __device__ __forceinline__ int xcd_slice(int g, int n) {
   return x * q + min(x, rem) + g / kXcd;
 }
 
+// Row of a BELL matrix times a vector of another precision (converted on
+// load).
 template <typename T, typename XT, int BS>
 __device__ __forceinline__ T bell_row_x(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
   const int bs = BS > 0 ? BS : A.bs;
@@ -712,9 +724,9 @@ __device__ __forceinline__ T bell_row_x(const DBELL<T>& A, const XT* __restrict_
     const XT* __restrict__ xc = x + (int64_t)c * bs;
     if (BS > 0) {
 #pragma unroll
-      for (int b = 0; b < BS; ++b) acc += v[b * 64] * (T)xc[b];
+      for (int b = 0; b < BS; ++b) acc += bell_val(v + b * 64) * (T)xc[b];
     } else {
-      for (int b = 0; b < bs; ++b) acc += v[b * 64] * (T)xc[b];
+      for (int b = 0; b < bs; ++b) acc += bell_val(v + b * 64) * (T)xc[b];
     }
   }
   return acc;
