@@ -556,9 +556,11 @@ __global__ void __launch_bounds__(kCgsBlock) k_cgs(const double* __restrict__ V,
   }
   const int64_t i = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x;
   const bool valid = i < n;
+  // the basis columns stream past the caches (nontemporal), which keeps the
+  // V-cycle's level-0 matrix resident in the last-level cache between steps
   double v[KMAX];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) v[k] = (valid && k < kk) ? V[(int64_t)k * ld + i] : 0.0;
+  for (int k = 0; k < KMAX; ++k) v[k] = (valid && k < kk) ? __builtin_nontemporal_load(V + (int64_t)k * ld + i) : 0.0;
   double wi = valid ? w[i] : 0.0;
   if (PASS >= 2) {
     double s = 0.0;
