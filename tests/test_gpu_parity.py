@@ -558,6 +558,37 @@ def test_nodal_lumping_on_rotated_problem(fmt, which):
             assert abs(info["iters"] - ref.iters) <= 1
 
 
+NODAL_2D = [
+    (dict(atilde="nodal", schur="block"), dict(atilde=2, schur=2)),
+    (dict(atilde="nodal", schur="block", smoother="uzawa", simple_alpha=0.7, jacobi_sweeps=2),
+     dict(atilde=2, schur=2, smoother=1, simple_alpha=0.7, jacobi_sweeps=2)),
+    (dict(schur="block", schur_sweeps=2), dict(schur=2, schur_sweeps=2)),
+]
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+@pytest.mark.parametrize("which", range(len(NODAL_2D)))
+def test_nodal_options_2d(fmt, which):
+    """The nodal options in 2D (2x2 fine and 3x3 coarse lumping blocks, 2x2
+    multiplier blocks), three levels: V-cycle and its transpose against the
+    oracle (FP64 1e-12, mixed 2e-5) and the converged solve's iteration
+    count."""
+    okw, lkw = NODAL_2D[which]
+    prob = make_contact_problem(2, (24, 24), (25, 24), rhs="random", seed=19)
+    kw = dict(max_levels=3, max_coarse_rows=50, nu_pre=3, nu_post=3)
+    oopts = OracleOptions(**kw, **okw)
+    lv = build_hierarchy(prob, oopts)
+    r = np.random.default_rng(23).standard_normal(prob.n)
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        s = _solver(prob, precision=prec, fmt=fmt, **kw, **lkw)
+        for tr in (False, True):
+            z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+            assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < tol, (okw, prec, tr)
+    ref = oracle_solve(lv, oopts, prob.b, rtol=1e-8, max_iters=300)
+    x, info = _solver(prob, fmt=fmt, **kw, **lkw).solve(torch.from_numpy(prob.b), rtol=1e-8, max_iters=300)
+    assert info["converged"] and abs(info["iters"] - ref.iters) <= 1, (info, ref.iters)
+
+
 def test_nodal_lumping_iterations_do_not_depend_on_the_angles():
     """The rotation experiment at the paper's size with the nodal lumping and
     nodal Schur blocks: each smoother's FP64 iteration count is the same for
