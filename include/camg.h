@@ -175,6 +175,12 @@ typedef struct {
                           steps behind the launches, so the device never waits for the
                           host; steps launched past convergence are discarded */
   double rtol;         /* stop when ||b - A x|| <= rtol ||b - A x0||        */
+  int32_t ortho;       /* Arnoldi orthogonalisation (m <= 63): 0 CGS2 with three passes over the
+                          basis (dots, update + dots, update + norm); 1 (default) CGS2 with two
+                          passes, the second projection's coefficients taken from the Gram matrix
+                          of the basis (h2 = h1 - V^T V h1, V^T V built from the update pass's own
+                          dots).  Equal in exact arithmetic; m > 63 always uses separate dot and
+                          update kernels */
 } amg_gmres_options;
 
 typedef struct {

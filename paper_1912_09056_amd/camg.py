@@ -88,6 +88,7 @@ class amg_gmres_options(Structure):
         ("fixed_iters", c_int32),
         ("lookahead", c_int32),
         ("rtol", c_double),
+        ("ortho", c_int32),
     ]
 
 
@@ -363,11 +364,12 @@ class AMGSolver:
         return z
 
     def solve(self, b, x0=None, transpose=False, m=50, rtol=1e-8, max_iters=1000, fixed_iters=0, lookahead=1,
-              stream=None):
-        """FGMRES solve; returns (x, result dict)."""
+              stream=None, ortho=1):
+        """FGMRES solve; returns (x, result dict).  ortho: 1 two-pass CGS2
+        (Gram-matrix second projection), 0 three-pass CGS2."""
         b = self._vec(b)
         x = self._vec(x0).clone() if x0 is not None else torch.zeros_like(b)
-        go = amg_gmres_options(m, max_iters, fixed_iters, lookahead, rtol)
+        go = amg_gmres_options(m, max_iters, fixed_iters, lookahead, rtol, ortho)
         res = amg_gmres_result()
         code = _check(self.lib.fgmres_solve(self.handle, int(transpose), _dptr(b), _dptr(x), byref(go), byref(res),
                                             _stream_ptr(stream)))

@@ -548,7 +548,7 @@ __global__ void __launch_bounds__(kCgsBlock) k_cgs(const double* __restrict__ V,
                                                    double* __restrict__ w, int64_t n,
                                                    const double* __restrict__ coef_in, double* __restrict__ partial) {
   constexpr int NW = kCgsBlock / 64;
-  __shared__ double lds[KMAX * NW];
+  __shared__ double lds[(KMAX + 1) * NW];
   __shared__ double coef[KMAX];
   if (PASS >= 2) {
     for (int k = threadIdx.x; k < kk; k += kCgsBlock) coef[k] = coef_in[k];
@@ -575,6 +575,10 @@ __global__ void __launch_bounds__(kCgsBlock) k_cgs(const double* __restrict__ V,
     const double t = sg_reduce<double, 64>(wi * wi);
     if (lane == 0) lds[wave] = t;
   } else {
+    if (PASS == 5) {  // the squared norm of the updated w goes after the kk dots
+      const double t2 = sg_reduce<double, 64>(wi * wi);
+      if (lane == 0) lds[KMAX * NW + wave] = t2;
+    }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) v[k] *= wi;
     const double t = wave_reduce_scatter<KMAX>(v);
@@ -587,6 +591,11 @@ __global__ void __launch_bounds__(kCgsBlock) k_cgs(const double* __restrict__ V,
     double t = 0.0;
     for (int q = 0; q < NW; ++q) t += lds[k * NW + q];
     partial[(int64_t)k * gridDim.x + blockIdx.x] = t;
+  }
+  if (PASS == 5 && threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < NW; ++q) t += lds[KMAX * NW + q];
+    partial[(int64_t)kk * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -1030,6 +1039,33 @@ __global__ void __launch_bounds__(kBlock) k_mdot_reduce(const double* __restrict
   for (int b = threadIdx.x; b < nb; b += kBlock) acc += partial[(int64_t)k * nb + b];
   const double t = block_sum(acc, lds);
   if (threadIdx.x == 0) h[k] = t;
+}
+
+// Second projection of CGS2 from the Gram matrix of the basis (two-pass
+// variant): column j of G = V^T V arrives as the previous step's dots of V
+// with the updated w, times 1/||w|| (its diagonal entry is 1); then
+// h2 = h1 - G h1 -- what a second pass over V would measure, up to rounding
+// of the first update -- and c = h1 + h2, the update's coefficients.
+// G is KMAX x KMAX column-major (kk <= 64), one workgroup.
+__global__ void __launch_bounds__(64) k_gram_step(double* __restrict__ G, int j, const double* __restrict__ gprev,
+                                                  const double* __restrict__ scale, const double* __restrict__ h1,
+                                                  double* __restrict__ h2, double* __restrict__ c) {
+  constexpr int L = 64;
+  const int k = threadIdx.x;
+  if (k < j) {
+    const double gk = gprev[k] * scale[0];
+    G[(int64_t)j * L + k] = gk;
+    G[(int64_t)k * L + j] = gk;
+  }
+  if (k == 0) G[(int64_t)j * L + j] = 1.0;
+  __syncthreads();
+  if (k <= j) {
+    double t = 0.0;
+    for (int q = 0; q <= j; ++q) t += G[(int64_t)q * L + k] * h1[q];
+    const double d = h1[k] - t;
+    h2[k] = d;
+    c[k] = h1[k] + d;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_gemv_acc(const double* __restrict__ M, int64_t ld, int kk,
@@ -1636,6 +1672,30 @@ void cgs_pass2(const double* V, int64_t ld, int kk, double* w, int64_t n, const 
   CAMG_KMAX_DISPATCH(kk, { k_cgs<KMAX, 2><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, w, n, h1, partial); });
   CAMG_LAUNCHED();
   k_mdot_reduce<<<kk, kBlock, 0, s>>>(partial, nb, h2);
+  CAMG_LAUNCHED();
+}
+
+void cgs2_gram(const double* V, int64_t ld, int kk, double* w, int64_t n, double* partial, double* h1, double* h2,
+               double* c, double* G, double* gn, const double* scale, double* H, int ldh, double* cs, double* sn,
+               double* g, double* out, double* out_host, hipStream_t s) {
+  if (kk < 1 || kk > 64) throw HipError{hipErrorInvalidValue, "cgs2_gram: kk out of range"};
+  const int nb = cgs_blocks(n);
+  const int j = kk - 1;
+  // pass 1: h1 = V^T w
+  CAMG_KMAX_DISPATCH(kk, { k_cgs<KMAX, 1><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, w, n, nullptr, partial); });
+  CAMG_LAUNCHED();
+  k_mdot_reduce<<<kk, kBlock, 0, s>>>(partial, nb, h1);
+  CAMG_LAUNCHED();
+  // h2 from the Gram matrix (column j from the previous step's dots gn)
+  k_gram_step<<<1, 64, 0, s>>>(G, j, gn, scale, h1, h2, c);
+  CAMG_LAUNCHED();
+  // pass 2: w -= V c, gn = V^T w (next Gram column) and ||w||^2 in gn[kk]
+  CAMG_KMAX_DISPATCH(kk, { k_cgs<KMAX, 5><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, w, n, c, partial); });
+  CAMG_LAUNCHED();
+  k_mdot_reduce<<<kk + 1, kBlock, 0, s>>>(partial, nb, gn);
+  CAMG_LAUNCHED();
+  // Hessenberg column h1 + h2, its Givens rotation, the residual estimate
+  k_arnoldi_update<<<1, 64, 0, s>>>(H, ldh, cs, sn, g, h1, h2, gn + kk, j, out, out_host);
   CAMG_LAUNCHED();
 }
 

@@ -216,6 +216,16 @@ void cgs_pass1(const double* V, int64_t ld, int kk, const double* w, int64_t n, 
                hipStream_t s);
 void cgs_pass2(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, double* partial,
                double* h2, hipStream_t s);
+// One CGS2 orthogonalisation of w against the kk columns of V with two
+// passes over V instead of three: h1 = V^T w; h2 = h1 - G h1 with the Gram
+// matrix G = V^T V (column kk-1 from the previous step's dots gn, scaled by
+// *scale = 1/||w_prev||; G is 64 x 64 column-major); w -= V (h1 + h2), whose
+// dots with V (the next Gram column) and squared norm land in gn[0..kk];
+// then the Hessenberg column, Givens rotation and result block as in
+// cgs_pass3.  In exact arithmetic h2 is what CGS2's second pass measures.
+void cgs2_gram(const double* V, int64_t ld, int kk, double* w, int64_t n, double* partial, double* h1, double* h2,
+               double* c, double* G, double* gn, const double* scale, double* H, int ldh, double* cs, double* sn,
+               double* g, double* out, double* out_host, hipStream_t s);
 void cgs_pass3(const double* V, int64_t ld, int kk, double* w, int64_t n, const double* h1, const double* h2,
                double* partial, double* H, int ldh, double* cs, double* sn, double* g, double* out, double* out_host,
                hipStream_t s);

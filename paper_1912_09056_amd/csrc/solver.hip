@@ -391,6 +391,7 @@ struct amg_handle {
   // Krylov workspace
   int m_alloc = 0;
   DBuf<double> V, Z, w, r, H, cs, sn, g, h1, h2, hn2, partial, out, y;
+  DBuf<double> Gram, gn, cc;  // two-pass CGS2: Gram matrix of the basis, next Gram column, update coefficients
   double* hbuf = nullptr;  // pinned host: [0,4) synchronous reads, then 4 doubles per pipelined slot
   double* hbuf_dev = nullptr;  // the same memory as a device address (kernels write the slots)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1007,6 +1008,9 @@ static void ensure_krylov(amg_handle& h, int m) {
   h.partial.alloc((size_t)((m + 1) * std::max(mdot_blocks(n), cgs_blocks(n))));
   h.out.alloc(4);
   h.y.alloc((size_t)m);
+  h.Gram.alloc(64 * 64);
+  h.gn.alloc(65);
+  h.cc.alloc(64);
   h.m_alloc = m;
 }
 
@@ -1073,7 +1077,11 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
       }
       {
         ProfScope ps(&h.prof, CAMG_KCLASS_ORTHO, s);
-        if (fused) {
+        if (fused && o.ortho == 1) {
+          cgs2_gram(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h1.p, h.h2.p, h.cc.p, h.Gram.p, h.gn.p,
+                    j ? h.out.p + 2 : nullptr, h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p, h.out.p,
+                    h.hbuf_dev + 4 + 4 * (j % amg_handle::kSlots), s);
+        } else if (fused) {
           cgs_pass1(h.V.p, n, j + 1, h.w.p, n, h.partial.p, h.h1.p, s);
           cgs_pass2(h.V.p, n, j + 1, h.w.p, n, h.h1.p, h.partial.p, h.h2.p, s);
           cgs_pass3(h.V.p, n, j + 1, h.w.p, n, h.h1.p, h.h2.p, h.partial.p, h.H.p, m + 1, h.cs.p, h.sn.p, h.g.p,
@@ -1237,6 +1245,7 @@ void amg_default_gmres_options(amg_gmres_options* o) {
   o->fixed_iters = 0;
   o->lookahead = 1;
   o->rtol = 1e-8;
+  o->ortho = 1;
 }
 
 }  // extern "C"
@@ -1512,7 +1521,8 @@ int fgmres_solve(amg_handle* h, int transpose, const double* b, double* x, const
     amg_gmres_options o;
     amg_default_gmres_options(&o);
     if (gopts) o = *gopts;
-    if (o.m < 1 || o.m > 512 || o.max_iters < 0 || o.fixed_iters < 0 || !(o.rtol >= 0.0))
+    if (o.m < 1 || o.m > 512 || o.max_iters < 0 || o.fixed_iters < 0 || !(o.rtol >= 0.0) || o.ortho < 0 ||
+        o.ortho > 1)
       api_fail(CAMG_ERR_INVALID_ARG, "invalid FGMRES options");
     need_device(h);
     CAMG_HIP(hipSetDevice(h->device));
