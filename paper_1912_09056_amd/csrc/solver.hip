@@ -631,15 +631,18 @@ LevelVecs<float>& vecs<float>(DevLevel& D) {
 }
 
 // One sweep with the nodal lumping blocks M = Atilde^-1 (the option that
-// makes the smoothers covariant under rotations of the node frames), from
-// generic kernels: block applies per node instead of the fused point-diagonal
-// kernels.  Forward (SIMPLE; Uzawa and Braess-Sarazin as in sweep):
+// makes the smoothers covariant under rotations of the node frames).
+// Forward (SIMPLE; Uzawa and Braess-Sarazin as in sweep):
 //   t = b_u - K z_u - G z_l,  w = J(t) (block Jacobi with M),
 //   q = -(b_l - B (z_u + w) - C z_l),  delta = S-relaxation(q),
 //   zn_l = z_l + alpha delta,  zn_u = z_u + w - alpha M G delta.
 // Adjoint: s_u = b_u - K^T z_u - B^T z_l, q = -(b_l - G^T (z_u + M^T s_u) -
 // C^T z_l), delta from S^T, zn_u = z_u + J^T(s_u - alpha B^T delta) with M^T.
-// From z = 0 (first) the input buffer is cleared and the general form runs.
+// On the level-0 blocked-ELL layout the residual and the block prediction
+// are one kernel; the back-substitution runs on the interface nodes only;
+// elsewhere the steps are separate products and block applies.  From z = 0
+// (first) the forward sweep starts from t = b_u and the adjoint one clears
+// the multiplier part of its input buffer (the V-cycle's own work buffer).
 template <typename T>
 static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const T* z, T* zn, bool first,
                         hipStream_t s) {
