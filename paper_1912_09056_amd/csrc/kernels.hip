@@ -1047,24 +1047,38 @@ __global__ void __launch_bounds__(kBlock) k_mdot_reduce(const double* __restrict
 // h2 = h1 - G h1 -- what a second pass over V would measure, up to rounding
 // of the first update -- and c = h1 + h2, the update's coefficients.
 // G is KMAX x KMAX column-major (kk <= 64), one workgroup.
-__global__ void __launch_bounds__(64) k_gram_step(double* __restrict__ G, int j, const double* __restrict__ gprev,
-                                                  const double* __restrict__ scale, const double* __restrict__ h1,
-                                                  double* __restrict__ h2, double* __restrict__ c) {
-  constexpr int L = 64;
-  const int k = threadIdx.x;
-  if (k < j) {
-    const double gk = gprev[k] * scale[0];
-    G[(int64_t)j * L + k] = gk;
-    G[(int64_t)k * L + j] = gk;
+__global__ void __launch_bounds__(256) k_gram_step(double* __restrict__ G, int j, const double* __restrict__ gprev,
+                                                   const double* __restrict__ scale, const double* __restrict__ h1,
+                                                   double* __restrict__ h2, double* __restrict__ c) {
+  constexpr int L = 64, P = 4;  // 4 partial sums per row k, over q in [16 p, 16 p + 16)
+  __shared__ double hs[L];
+  __shared__ double part[P][L];
+  const int k = threadIdx.x % L, p = threadIdx.x / L;
+  if (p == 0) {
+    if (k < j) {
+      const double gk = gprev[k] * scale[0];
+      G[(int64_t)j * L + k] = gk;
+      G[(int64_t)k * L + j] = gk;
+    }
+    if (k == j) G[(int64_t)j * L + j] = 1.0;
+    hs[k] = k <= j ? h1[k] : 0.0;
   }
-  if (k == 0) G[(int64_t)j * L + j] = 1.0;
   __syncthreads();
+  double t = 0.0;
   if (k <= j) {
-    double t = 0.0;
-    for (int q = 0; q <= j; ++q) t += G[(int64_t)q * L + k] * h1[q];
-    const double d = h1[k] - t;
+#pragma unroll
+    for (int u = 0; u < L / P; ++u) {
+      const int q = p * (L / P) + u;
+      if (q <= j) t += G[(int64_t)q * L + k] * hs[q];
+    }
+  }
+  part[p][k] = t;
+  __syncthreads();
+  if (p == 0 && k <= j) {
+    const double gh = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
+    const double d = hs[k] - gh;
     h2[k] = d;
-    c[k] = h1[k] + d;
+    c[k] = hs[k] + d;
   }
 }
 
@@ -1687,7 +1701,7 @@ void cgs2_gram(const double* V, int64_t ld, int kk, double* w, int64_t n, double
   k_mdot_reduce<<<kk, kBlock, 0, s>>>(partial, nb, h1);
   CAMG_LAUNCHED();
   // h2 from the Gram matrix (column j from the previous step's dots gn)
-  k_gram_step<<<1, 64, 0, s>>>(G, j, gn, scale, h1, h2, c);
+  k_gram_step<<<1, 256, 0, s>>>(G, j, gn, scale, h1, h2, c);
   CAMG_LAUNCHED();
   // pass 2: w -= V c, gn = V^T w (next Gram column) and ||w||^2 in gn[kk]
   CAMG_KMAX_DISPATCH(kk, { k_cgs<KMAX, 5><<<nb, kCgsBlock, 0, s>>>(V, ld, kk, w, n, c, partial); });
@@ -1695,7 +1709,8 @@ void cgs2_gram(const double* V, int64_t ld, int kk, double* w, int64_t n, double
   k_mdot_reduce<<<kk + 1, kBlock, 0, s>>>(partial, nb, gn);
   CAMG_LAUNCHED();
   // Hessenberg column h1 + h2, its Givens rotation, the residual estimate
-  k_arnoldi_update<<<1, 64, 0, s>>>(H, ldh, cs, sn, g, h1, h2, gn + kk, j, out, out_host);
+  // (the squared norm is already reduced: one partial)
+  k_cgs_finish<<<1, kBlock, 0, s>>>(gn + kk, 1, kk, h1, h2, H, ldh, cs, sn, g, out, out_host);
   CAMG_LAUNCHED();
 }
 
