@@ -54,48 +54,6 @@ namespace {
 
 [[noreturn]] void fail(int code, const std::string& m) { throw SetupError{code, m}; }
 
-// Host threads for the row-independent products: OMP_NUM_THREADS when set
-// (the process's CPU share), else the hardware count, at most 64.
-int setup_threads() {
-  int n = 0;
-  if (const char* e = std::getenv("OMP_NUM_THREADS")) n = std::atoi(e);
-  if (n <= 0) n = (int)std::thread::hardware_concurrency();
-  return std::max(1, std::min(n, 64));
-}
-
-// Runs body(c, t) for every chunk c in [0, n_chunks) on nt threads (t is
-// the thread's index in [0, nt), for per-thread scratch), chunks handed out
-// in increasing order.  Results must depend only on the chunk, never on the
-// thread, so the output is identical for any thread count.  The first
-// exception thrown by a body is rethrown after all threads end.
-template <typename Body>
-void parallel_chunks(int64_t n_chunks, int nt, Body body) {
-  if (nt <= 1) {
-    for (int64_t c = 0; c < n_chunks; ++c) body(c, 0);
-    return;
-  }
-  std::atomic<int64_t> next{0};
-  std::exception_ptr err;
-  std::atomic<bool> failed{false};
-  auto work = [&](int t) {
-    for (;;) {
-      const int64_t c = next.fetch_add(1);
-      if (c >= n_chunks || failed.load()) return;
-      try {
-        body(c, t);
-      } catch (...) {
-        if (!failed.exchange(true)) err = std::current_exception();
-        return;
-      }
-    }
-  };
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
-  work(0);
-  for (auto& t : pool) t.join();
-  if (err) std::rethrow_exception(err);
-}
-
 // Rows [r0, r1) of a CSR result computed by one chunk.
 struct RowBlock {
   std::vector<int64_t> len;
@@ -854,6 +812,7 @@ void coarse_inverse(HostLevel& L) {
 HostLevel coarsen(HostLevel& L, const SetupOptions& opt) {
   const int bs = L.bs_u;
   const int64_t nn = L.n_u() / bs;
+  PhaseTimer pt_all("coarsen (level total)");
   L.dirichlet = find_dirichlet(L.K, L.G);
   std::vector<uint8_t> active((size_t)nn, 0);
   for (int64_t a = 0; a < nn; ++a)
@@ -861,9 +820,12 @@ HostLevel coarsen(HostLevel& L, const SetupOptions& opt) {
       if (!L.dirichlet[a * bs + c]) active[a] = 1;
   std::vector<int64_t> gp;
   std::vector<int32_t> gi;
-  node_graph(L, gp, gi);
-  L.n_agg_u = aggregate_nodes(gp, gi, active, L.agg_u);
-  L.n_agg_l = lagmult_aggregation(L, L.agg_l);
+  {
+    PhaseTimer pt("node graph + aggregation");
+    node_graph(L, gp, gi);
+    L.n_agg_u = aggregate_nodes(gp, gi, active, L.agg_u);
+    L.n_agg_l = lagmult_aggregation(L, L.agg_l);
+  }
 
   HostLevel Cn;
   std::vector<double> nsc_u, nsc_l;
@@ -878,10 +840,13 @@ HostLevel coarsen(HostLevel& L, const SetupOptions& opt) {
                                                        nodal_lumping_inverse(L.K, L.bs_u, 1.0), L.bs_u)
                             : smooth_prolongator(L.K, L.P_u, opt.sa_omega);
   HostCSR Ru = transpose(L.P_u), Rl = transpose(L.P_l);
-  Cn.K = galerkin(Ru, L.K, L.P_u);
-  Cn.G = galerkin(Ru, L.G, L.P_l);
-  Cn.B = galerkin(Rl, L.B, L.P_u);
-  Cn.C = galerkin(Rl, L.C, L.P_l);
+  {
+    PhaseTimer pt("galerkin");
+    Cn.K = galerkin(Ru, L.K, L.P_u);
+    Cn.G = galerkin(Ru, L.G, L.P_l);
+    Cn.B = galerkin(Rl, L.B, L.P_u);
+    Cn.C = galerkin(Rl, L.C, L.P_l);
+  }
   Cn.bs_u = L.n_ns_u;
   Cn.bs_l = L.n_ns_l;
   Cn.n_ns_u = L.n_ns_u;
@@ -939,7 +904,11 @@ void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt) {
     levels.push_back(std::move(nxt));
   }
   const size_t n_smooth = opt.simple_coarse ? levels.size() : levels.size() - 1;
-  for (size_t l = 0; l < n_smooth; ++l) smoother_data(levels[l], opt);
+  {
+    PhaseTimer pt("smoother data");
+    for (size_t l = 0; l < n_smooth; ++l) smoother_data(levels[l], opt);
+  }
+  PhaseTimer pt("coarsest inverse");
   if (!opt.simple_coarse) coarse_inverse(levels.back());
 }
 

@@ -7,8 +7,15 @@
 // uploaded.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <exception>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace camg {
@@ -25,6 +32,64 @@ struct HostCSR {
     rp.assign((size_t)r + 1, 0);
     ci.clear();
     v.clear();
+  }
+};
+
+// Host threads for the row-independent products: OMP_NUM_THREADS when set
+// (the process's CPU share), else the hardware count, at most 64.
+inline int setup_threads() {
+  int n = 0;
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) n = std::atoi(e);
+  if (n <= 0) n = (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(n, 64));
+}
+
+// Runs body(c, t) for every chunk c in [0, n_chunks) on nt threads (t is
+// the thread's index in [0, nt), for per-thread scratch), chunks handed out
+// in increasing order.  Results must depend only on the chunk, never on the
+// thread, so the output is identical for any thread count.  The first
+// exception thrown by a body is rethrown after all threads end.
+template <typename Body>
+void parallel_chunks(int64_t n_chunks, int nt, Body body) {
+  if (nt <= 1) {
+    for (int64_t c = 0; c < n_chunks; ++c) body(c, 0);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::exception_ptr err;
+  std::atomic<bool> failed{false};
+  auto work = [&](int t) {
+    for (;;) {
+      const int64_t c = next.fetch_add(1);
+      if (c >= n_chunks || failed.load()) return;
+      try {
+        body(c, t);
+      } catch (...) {
+        if (!failed.exchange(true)) err = std::current_exception();
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& t : pool) t.join();
+  if (err) std::rethrow_exception(err);
+}
+
+// Setup phase timing on stderr when CAMG_SETUP_TIMING=1 (diagnostics only).
+struct PhaseTimer {
+  const char* name;
+  std::chrono::steady_clock::time_point t0;
+  explicit PhaseTimer(const char* n) : name(n), t0(std::chrono::steady_clock::now()) {}
+  ~PhaseTimer() {
+    static const bool on = [] {
+      const char* e = std::getenv("CAMG_SETUP_TIMING");
+      return e && e[0] == '1';
+    }();
+    if (!on) return;
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[camg setup] %-28s %8.3f s\n", name, sec);
   }
 };
 

@@ -156,52 +156,62 @@ static HostBell make_bell(const HostCSR& A, int bs) {
   B.bs = bs;
   B.n_nodes = (int32_t)(A.nrows / bs);
   B.n_slices = (B.n_nodes + 63) / 64;
-  std::vector<int64_t> nptr((size_t)B.n_nodes + 1, 0);
-  std::vector<int32_t> nb;
-  std::vector<int32_t> tmp;
-  for (int32_t i = 0; i < B.n_nodes; ++i) {
-    tmp.clear();
-    for (int a = 0; a < bs; ++a) {
-      const int64_t r = (int64_t)i * bs + a;
-      for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) tmp.push_back(A.ci[k] / bs);
+  const int nt = setup_threads();
+  // sorted distinct block columns of every node, one slice (64 nodes) per chunk
+  std::vector<std::vector<int32_t>> sl_cols((size_t)B.n_slices);
+  std::vector<std::vector<int32_t>> sl_cnt((size_t)B.n_slices);
+  parallel_chunks(B.n_slices, nt, [&](int64_t sl, int) {
+    std::vector<int32_t> tmp;
+    auto& cols = sl_cols[(size_t)sl];
+    auto& cnt = sl_cnt[(size_t)sl];
+    for (int32_t i = (int32_t)sl * 64; i < std::min(B.n_nodes, (int32_t)sl * 64 + 64); ++i) {
+      tmp.clear();
+      for (int a = 0; a < bs; ++a) {
+        const int64_t r = (int64_t)i * bs + a;
+        for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) tmp.push_back(A.ci[k] / bs);
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      cols.insert(cols.end(), tmp.begin(), tmp.end());
+      cnt.push_back((int32_t)tmp.size());
     }
-    std::sort(tmp.begin(), tmp.end());
-    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-    nb.insert(nb.end(), tmp.begin(), tmp.end());
-    nptr[i + 1] = (int64_t)nb.size();
-  }
-  B.n_blocks = (int64_t)nb.size();
+  });
   B.slice_ptr.assign((size_t)B.n_slices + 1, 0);
+  int64_t nblk = 0;
   for (int32_t sl = 0; sl < B.n_slices; ++sl) {
-    int64_t w = 0;
-    for (int32_t i = sl * 64; i < std::min(B.n_nodes, sl * 64 + 64); ++i) w = std::max(w, nptr[i + 1] - nptr[i]);
-    B.slice_ptr[sl + 1] = B.slice_ptr[sl] + (int32_t)w;
+    int32_t w = 0;
+    for (int32_t c : sl_cnt[(size_t)sl]) w = std::max(w, c);
+    B.slice_ptr[sl + 1] = B.slice_ptr[sl] + w;
+    nblk += (int64_t)sl_cols[(size_t)sl].size();
   }
+  B.n_blocks = nblk;
   const int64_t npos = B.slice_ptr[B.n_slices];
   B.bcol.assign((size_t)(npos * 64), 0);
   B.val.assign((size_t)(npos * 64 * bs * bs), 0.0);
-  for (int32_t i = 0; i < B.n_nodes; ++i) {
-    const int32_t sl = i / 64, lane = i % 64;
-    const int64_t w = B.slice_ptr[sl + 1] - B.slice_ptr[sl];
-    const int64_t cnt = nptr[i + 1] - nptr[i];
-    for (int64_t k = 0; k < w; ++k)
-      B.bcol[(size_t)((B.slice_ptr[sl] + k) * 64 + lane)] = k < cnt ? nb[(size_t)(nptr[i] + k)] : i;
-  }
   B.pos.resize((size_t)A.nnz());
-  for (int64_t r = 0; r < A.nrows; ++r) {
-    const int32_t i = (int32_t)(r / bs), a = (int32_t)(r % bs);
-    const int32_t sl = i / 64, lane = i % 64;
-    const int32_t* b0 = nb.data() + nptr[i];
-    const int32_t* b1 = nb.data() + nptr[i + 1];
-    for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
-      const int32_t bc = A.ci[k] / bs, b = A.ci[k] % bs;
-      const int64_t kk = std::lower_bound(b0, b1, bc) - b0;
-      const int64_t p = B.slice_ptr[sl] + kk;
-      const int64_t idx = (p * bs * bs + a * bs + b) * 64 + lane;
-      B.val[(size_t)idx] = A.v[k];
-      B.pos[(size_t)k] = idx;
+  parallel_chunks(B.n_slices, nt, [&](int64_t sl, int) {
+    const auto& cols = sl_cols[(size_t)sl];
+    const auto& cnt = sl_cnt[(size_t)sl];
+    const int64_t p0 = B.slice_ptr[sl], w = B.slice_ptr[sl + 1] - p0;
+    int64_t off = 0;
+    for (int32_t lane = 0; lane < (int32_t)cnt.size(); ++lane) {
+      const int32_t i = (int32_t)sl * 64 + lane;
+      const int32_t* b0 = cols.data() + off;
+      const int32_t* b1 = b0 + cnt[(size_t)lane];
+      for (int64_t k = 0; k < w; ++k) B.bcol[(size_t)((p0 + k) * 64 + lane)] = k < cnt[(size_t)lane] ? b0[k] : i;
+      for (int a = 0; a < bs; ++a) {
+        const int64_t r = (int64_t)i * bs + a;
+        for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+          const int32_t bc = A.ci[k] / bs, b = A.ci[k] % bs;
+          const int64_t kk = std::lower_bound(b0, b1, bc) - b0;
+          const int64_t idx = ((p0 + kk) * bs * bs + a * bs + b) * 64 + lane;
+          B.val[(size_t)idx] = A.v[k];
+          B.pos[(size_t)k] = idx;
+        }
+      }
+      off += cnt[(size_t)lane];
     }
-  }
+  });
   return B;
 }
 
@@ -500,13 +510,15 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
     const bool f32 = mixed;
     D.n_u = H.n_u();
     D.n_l = H.n_l();
+    PhaseTimer pt_level(l == 0 ? "upload level 0" : "upload coarse level");
     upload_mat(D.K, H.K, f64, f32, s);
     upload_mat(D.G, H.G, f64, f32, s);
     upload_mat(D.B, H.B, f64, f32, s);
     upload_mat(D.C, H.C, f64, f32, s);
     std::vector<int32_t>* perms[4] = {nullptr, nullptr, nullptr, nullptr};
     if (l == 0) perms[0] = &h.perm_K, perms[1] = &h.perm_G, perms[2] = &h.perm_B, perms[3] = &h.perm_C;
-    upload_mat(D.KT, transpose(H.K, perms[0]), f64, f32, s);
+    const HostCSR KT = transpose(H.K, perms[0]);
+    upload_mat(D.KT, KT, f64, f32, s);
     upload_mat(D.GT, transpose(H.G, perms[1]), f64, f32, s);
     upload_mat(D.BT, transpose(H.B, perms[2]), f64, f32, s);
     upload_mat(D.CT, transpose(H.C, perms[3]), f64, f32, s);
@@ -518,7 +530,7 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       D.bell = (fmt == CAMG_SPMV_BELL) || (fmt == CAMG_SPMV_AUTO && slices >= 512);
       if (D.bell && H.bs_u > 0 && H.n_u() % H.bs_u == 0) {
         HostBell hb = make_bell(H.K, H.bs_u);
-        HostBell hbt = make_bell(transpose(H.K), H.bs_u);
+        HostBell hbt = make_bell(KT, H.bs_u);
         if (l == 0) {
           std::vector<int64_t> posT((size_t)H.K.nnz());
           for (int64_t k = 0; k < H.K.nnz(); ++k) posT[(size_t)k] = hbt.pos[(size_t)h.perm_K[(size_t)k]];
@@ -538,7 +550,7 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
     if (!D.bell && l > 0 && h.opts.spmv_format == CAMG_SPMV_AUTO &&
         !(coarsest && h.opts.coarse_solver == CAMG_COARSE_LU)) {
       upload_rowblock(D.K, H.K, H.bs_u, f64, f32, s);
-      upload_rowblock(D.KT, transpose(H.K), H.bs_u, f64, f32, s);
+      upload_rowblock(D.KT, KT, H.bs_u, f64, f32, s);
     }
     if (!coarsest) {
       const bool t64 = !mixed;
@@ -1356,7 +1368,11 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
   return guarded([&]() -> int {
     if (!out) api_fail(CAMG_ERR_INVALID_ARG, "NULL output handle");
     *out = nullptr;
-    auto h = build_host(p, opts);
+    PhaseTimer pt_all("amg_setup total");
+    auto h = [&] {
+      PhaseTimer pt("host import + hierarchy");
+      return build_host(p, opts);
+    }();
     hipStream_t s = as_stream(stream);
     CAMG_HIP(hipGetDevice(&h->device));
     CAMG_HIP(hipEventCreate(&h->ev0));
@@ -1365,7 +1381,10 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
                            hipHostMallocMapped | hipHostMallocCoherent));
     CAMG_HIP(hipHostGetDevicePointer((void**)&h->hbuf_dev, h->hbuf, 0));
     for (auto& e : h->evq) CAMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    upload_hierarchy(*h, s);
+    {
+      PhaseTimer pt("device upload");
+      upload_hierarchy(*h, s);
+    }
     *out = h.release();
     return CAMG_OK;
   });
