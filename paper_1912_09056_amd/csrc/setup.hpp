@@ -77,6 +77,15 @@ void parallel_chunks(int64_t n_chunks, int nt, Body body) {
   if (err) std::rethrow_exception(err);
 }
 
+// body(i0, i1) over [0, n) in chunks of `grain` on the setup threads
+// (element-wise loops whose result does not depend on the split).
+template <typename Body>
+void parallel_for(int64_t n, Body body, int64_t grain = 1 << 16) {
+  const int64_t n_chunks = (n + grain - 1) / grain;
+  const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n_chunks, 1));
+  parallel_chunks(n_chunks, nt, [&](int64_t c, int) { body(c * grain, std::min(n, (c + 1) * grain)); });
+}
+
 // Setup phase timing on stderr when CAMG_SETUP_TIMING=1 (diagnostics only).
 struct PhaseTimer {
   const char* name;

@@ -94,7 +94,9 @@ static void upload_mat(DevMat& D, const HostCSR& H, bool f64, bool f32, hipStrea
   if (f64) D.v64.upload(H.v, s);
   if (f32) {
     std::vector<float> v32(H.v.size());
-    for (size_t i = 0; i < H.v.size(); ++i) v32[i] = (float)H.v[i];
+    parallel_for((int64_t)v32.size(), [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) v32[(size_t)i] = (float)H.v[(size_t)i];
+    });
     D.v32.upload(v32, s);
   }
   CAMG_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
@@ -242,7 +244,10 @@ static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipSt
   D.bcol.upload(H.bcol, s);
   if (f64) D.v64.upload(H.val, s);
   if (f32) {
-    std::vector<float> v32(H.val.begin(), H.val.end());
+    std::vector<float> v32(H.val.size());
+    parallel_for((int64_t)v32.size(), [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) v32[(size_t)i] = (float)H.val[(size_t)i];
+    });
     D.v32.upload(v32, s);
     CAMG_HIP(hipStreamSynchronize(s));
   }
@@ -533,7 +538,9 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
         HostBell hbt = make_bell(KT, H.bs_u);
         if (l == 0) {
           std::vector<int64_t> posT((size_t)H.K.nnz());
-          for (int64_t k = 0; k < H.K.nnz(); ++k) posT[(size_t)k] = hbt.pos[(size_t)h.perm_K[(size_t)k]];
+          parallel_for(H.K.nnz(), [&](int64_t k0, int64_t k1) {
+            for (int64_t k = k0; k < k1; ++k) posT[(size_t)k] = hbt.pos[(size_t)h.perm_K[(size_t)k]];
+          });
           h.d_bpos_K.upload(hb.pos, s);
           h.d_bpos_KT.upload(posT, s);
           CAMG_HIP(hipStreamSynchronize(s));
