@@ -296,3 +296,20 @@ def test_host_nodal_lumping_matches_oracle(smoother, prolongator):
     with pytest.raises(CamgError) as e:  # the nodal blocks are the prediction's relaxation too
         AMGSolver.from_problem(prob, AMGOptions(max_levels=2, atilde=2, jacobi_diag=1), host_only=True)
     assert e.value.code == -1
+
+
+def test_block_schur_needs_node_contiguous_multipliers():
+    # the nodal Schur blocks take the d multipliers of a node as consecutive
+    # dofs; a problem whose lm_node map is not j / d is a shape error (-2)
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver, CamgError
+
+    p = make_workload("contact3d_6")
+    ln = np.arange(p.n_lam) // 3
+    ln[[0, 3]] = ln[[3, 0]]  # swap two multipliers between nodes 0 and 1
+    with pytest.raises(CamgError) as e:
+        AMGSolver(3, p.K, p.G, p.B, p.C, p.slave_dofs, p.master_dofs, nullspace=p.nullspace, lm_node=ln,
+                  options=AMGOptions(max_levels=2, schur=2), host_only=True)
+    assert e.value.code == -2
+    # the point options accept any pseudo-node map
+    AMGSolver(3, p.K, p.G, p.B, p.C, p.slave_dofs, p.master_dofs, nullspace=p.nullspace, lm_node=ln,
+              options=AMGOptions(max_levels=2), host_only=True)
