@@ -92,7 +92,7 @@ def test_gradients_40_central_differences(prec):
 # sweeps standing in for its ILU on the Schur system; the plain settings stall
 # on lognormal(0, 2) moduli (the diagonal Schur step is not a convergent
 # splitting there)
-ROBUST = dict(prolongator=1, schur=1, schur_sweeps=8, jacobi_sweeps=2, nu_pre=3, nu_post=3)
+ROBUST = dict(prolongator=1, schur=1, schur_sweeps=8, jacobi_sweeps=2, nu_pre=3, nu_post=3)  # AMGOptions.robust()
 
 
 def _large_case(name, levels, **opts):

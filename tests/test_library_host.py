@@ -313,3 +313,13 @@ def test_block_schur_needs_node_contiguous_multipliers():
     # the point options accept any pseudo-node map
     AMGSolver(3, p.K, p.G, p.B, p.C, p.slave_dofs, p.master_dofs, nullspace=p.nullspace, lm_node=ln,
               options=AMGOptions(max_levels=2), host_only=True)
+
+
+def test_option_presets():
+    from paper_1912_09056_amd.camg import AMGOptions
+
+    r = AMGOptions.robust(max_levels=5)
+    assert (r.prolongator, r.schur, r.schur_sweeps, r.jacobi_sweeps, r.nu_pre, r.nu_post, r.max_levels) == \
+        (1, 1, 8, 2, 3, 3, 5)
+    q = AMGOptions.rotation_robust()
+    assert (q.atilde, q.schur, q.jacobi_diag) == (2, 2, 0)
