@@ -5,6 +5,11 @@ Backward (hand-written adjoint): A^T lam = dL/dx solved by FGMRES with the
 transposed V-cycle on the same hierarchy; dL/db = lam and
 dL/dK_ij = -lam_i x_j on K's stored entries (amg_grad_K).  Both solves and
 the gradient sampling run in the HIP library.
+
+The solver holds one set of level-0 values at a time, so backward first
+writes the forward's K values back: another forward (or a no-grad solve with
+other values) between a forward and its backward then cannot change the
+operator the adjoint solves with.
 """
 from __future__ import annotations
 
@@ -24,13 +29,21 @@ class ContactSolve(torch.autograd.Function):
         ctx.solver = solver
         ctx.rtol = rtol
         ctx.m = m
-        ctx.save_for_backward(x)
+        ctx.has_K = K_val is not None
+        if K_val is not None:
+            ctx.save_for_backward(x, K_val)
+        else:
+            ctx.save_for_backward(x)
         return x
 
     @staticmethod
     def backward(ctx, gx: torch.Tensor):
-        (x,) = ctx.saved_tensors
+        saved = ctx.saved_tensors
+        x = saved[0]
         solver = ctx.solver
+        if ctx.has_K:
+            # the operator of this forward, whatever values later calls loaded
+            solver.update_fine_values(K_val=saved[1].detach())
         lam, info = solver.solve(gx.contiguous(), transpose=True, rtol=ctx.rtol, m=ctx.m)
         if not info["converged"]:
             raise RuntimeError(f"adjoint solve did not converge: {info}")

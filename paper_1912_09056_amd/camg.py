@@ -244,16 +244,18 @@ def _ptr(a, ctype):
 
 
 def _csr_arrays(M, nrows, ncols):
-    """(rowptr int64, col int32, val float64) from a scipy-like CSR matrix."""
+    """(rowptr int64, col int32, val float64, shape) from a scipy-like CSR
+    matrix; None is an empty nrows x ncols block.  The shape is passed on as
+    the matrix has it: the library checks it against the system."""
     if M is None:
-        return np.zeros(nrows + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float64)
+        return np.zeros(nrows + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float64), (nrows, ncols)
     M = M.tocsr()
     M.sort_indices()
-    assert M.shape == (nrows, ncols), (M.shape, nrows, ncols)
     return (
         np.ascontiguousarray(M.indptr, dtype=np.int64),
         np.ascontiguousarray(M.indices, dtype=np.int32),
         np.ascontiguousarray(M.data, dtype=np.float64),
+        M.shape,
     )
 
 
@@ -290,9 +292,9 @@ class AMGSolver:
         prob = amg_problem()
         prob.dim = dim
         for name, M, r, c in (("K", K, n_u, n_u), ("G", G, n_u, n_l), ("B", B, n_l, n_u), ("C", C, n_l, n_l)):
-            rp, ci, v = _csr_arrays(M, r, c)
+            rp, ci, v, (mr, mc) = _csr_arrays(M, r, c)
             keep += [rp, ci, v]
-            setattr(prob, name, amg_csr(r, c, ci.size, _ptr(rp, c_int64), _ptr(ci, c_int32), _ptr(v, c_double)))
+            setattr(prob, name, amg_csr(mr, mc, ci.size, _ptr(rp, c_int64), _ptr(ci, c_int32), _ptr(v, c_double)))
         sd = np.ascontiguousarray(slave_dofs, dtype=np.int32)
         md = np.ascontiguousarray(master_dofs, dtype=np.int32)
         keep += [sd, md]
@@ -414,7 +416,8 @@ class AMGSolver:
                 keep.append(t)
                 args.append(_dptr(t))
         _check(self.lib.amg_update_fine_values(self.handle, *args, _stream_ptr(stream)))
-        torch.cuda.current_stream(self.device).synchronize()
+        # the copies read the temporaries in `keep` asynchronously on that stream
+        (stream if stream is not None else torch.cuda.current_stream(self.device)).synchronize()
 
     def profile_enable(self, mask: int):
         _check(self.lib.amg_profile_enable(self.handle, mask))

@@ -118,7 +118,8 @@ def test_fgmres_fixed_iterations_fp64(case):
     prob, lv, oopts, kw = case
     s = _solver(prob, **kw)
     for tr in (False, True):
-        for k, m in ((7, 50), (23, 10)):
+        # (45, 50) runs the widest CGS2 kernels (up to 64 basis vectors per pass)
+        for k, m in ((7, 50), (23, 10), (45, 50)):
             ref = oracle_solve(lv, oopts, prob.b, transpose=tr, m=m, fixed_iters=k)
             x, info = s.solve(torch.from_numpy(prob.b), transpose=tr, m=m, fixed_iters=k)
             assert info["iters"] == k
@@ -190,6 +191,43 @@ def test_autograd_dense_reference(fmt):
         assert _rel(x.detach().cpu().numpy(), x_ref) < 1e-10
         assert _rel(b.grad.cpu().numpy(), lam_ref) < 1e-9
         assert _rel(Kv.grad.cpu().numpy(), gK_ref) < 1e-9
+
+
+def test_autograd_backward_uses_its_forward_operator():
+    """Two forwards with different K values, then the backward of the first:
+    the adjoint solve and dL/dK use the first forward's operator (the dense
+    reference of K1), not the values the second forward left in the solver."""
+    from paper_1912_09056_amd import contact_solve
+
+    prob = make_workload("contact3d_6")
+    top = prob.top_dofs
+    s = _solver(prob, fmt=2, max_levels=2)
+    K1 = prob.K.copy()
+    K2 = prob.K.copy()
+    K2.data = K2.data * (1.0 + 0.2 * np.random.default_rng(31).random(K2.nnz))
+    K2 = (K2 + K2.T) * 0.5  # same pattern, other values
+    K2 = K2.tocsr()
+    K2.sort_indices()
+    assert np.array_equal(K2.indices, K1.indices)
+    A1 = sp.bmat([[K1, prob.G], [prob.B, prob.C]]).toarray()
+    x_ref = np.linalg.solve(A1, prob.b)
+    g = np.zeros(prob.n)
+    g[top] = x_ref[top]
+    lam_ref = np.linalg.solve(A1.T, g)
+    rows = np.repeat(np.arange(prob.n_u), np.diff(K1.indptr))
+    gK_ref = -lam_ref[rows] * x_ref[K1.indices]
+    Kv1 = torch.tensor(K1.data, dtype=torch.float64, device="cuda", requires_grad=True)
+    Kv2 = torch.tensor(K2.data, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(prob.b, dtype=torch.float64, device="cuda", requires_grad=True)
+    tt = torch.from_numpy(top).cuda()
+    x1 = contact_solve(s, Kv1, b, rtol=1e-12)
+    x2 = contact_solve(s, Kv2, b, rtol=1e-12)
+    assert _rel(x1.detach().cpu().numpy(), x_ref) < 1e-10
+    assert _rel(x2.detach().cpu().numpy(), x_ref) > 1e-3  # the second operator differs
+    (0.5 * (x1[tt] ** 2).sum()).backward()
+    assert _rel(b.grad.cpu().numpy(), lam_ref) < 1e-9
+    assert _rel(Kv1.grad.cpu().numpy(), gK_ref) < 1e-9
+    assert Kv2.grad is None
 
 
 @pytest.mark.parametrize("fmt", [1, 2])
@@ -677,6 +715,10 @@ def test_bench_workload_parity():
     assert _rel(z, oracle_vcycle(lv, r, oopts)) < 1e-12
     zt = s.vcycle(torch.from_numpy(r), transpose=True).cpu().numpy()
     assert _rel(zt, oracle_vcycle(lv, r, oopts, transpose=True)) < 1e-12
+    sm = _solver(prob, precision=1, **kw)
+    for tr, ref in ((False, z), (True, zt)):
+        assert _rel(sm.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy(), ref) < 2e-5, tr
+    del sm
     A = prob.full_matrix()
     sc = _solver(prob, fmt=1, **kw)
     assert _rel(sc.vcycle(torch.from_numpy(r)).cpu().numpy(), z) < 1e-13
@@ -726,3 +768,24 @@ def test_lookahead_depth_does_not_change_results():
                 ref = (x.cpu(), info["iters"])
             else:
                 assert info["iters"] == ref[1] and torch.equal(x.cpu(), ref[0]), (la, m)
+
+
+def test_bench_workload_fgmres_fixed_iterations():
+    """FGMRES(50) on the 40^3 / 41x41x40 workload for 60 fixed iterations, one
+    full restart cycle plus ten steps, forward and transposed, against the
+    oracle (FP64, 1e-10): the widest two-pass CGS2 kernels (up to 51 basis
+    vectors per pass) in the launch configuration the benchmark times."""
+    prob = make_workload("contact3d_40")
+    kw = dict(max_levels=4)
+    oopts = OracleOptions(**kw)
+    lv = build_hierarchy(prob, oopts)
+    s = _solver(prob, **kw)
+    for tr in (False, True):
+        ref = oracle_solve(lv, oopts, prob.b, transpose=tr, m=50, fixed_iters=60)
+        x, info = s.solve(torch.from_numpy(prob.b), transpose=tr, m=50, fixed_iters=60)
+        err = _rel(x.cpu().numpy(), ref.x)
+        print(f"[fixed60] tr={tr} err={err:.2e} res={info['rel_res_true']:.3e} oracle={ref.rel_res_true:.3e}",
+              flush=True)
+        assert info["iters"] == 60 and info["restarts"] == 1
+        assert err < 1e-10, (tr, err)
+        assert abs(info["rel_res_true"] - ref.rel_res_true) <= 1e-6 * ref.rel_res_true
