@@ -52,7 +52,8 @@ extern "C" {
 
 typedef struct amg_handle amg_handle;
 
-/* Compressed sparse row matrix, host pointers.  rowptr has nrows+1 entries
+/* Compressed sparse row matrix (host pointers unless the problem says
+ * device_ptrs = 1).  rowptr has nrows+1 entries
  * starting at 0; column indices are sorted and unique within each row;
  * nnz = rowptr[nrows] must be below 2^31.  An all-empty block (nnz = 0) may
  * pass NULL col/val. */
@@ -63,8 +64,10 @@ typedef struct {
   const double* val;
 } amg_csr;
 
-/* Problem statement, host pointers (Sec. 2.3 blocks; Sec. 4.2/4.3 interface
- * data).  Layout rules:
+/* Problem statement (Sec. 2.3 blocks; Sec. 4.2/4.3 interface data).  Its
+ * arrays are host pointers, or device pointers with device_ptrs = 1 (then
+ * amg_setup copies them to the host once, since the hierarchy is built
+ * there; sizes always come from this structure).  Layout rules:
  *  - displacement dofs are node-major: dof = node * dim + component;
  *  - slave_dofs / master_dofs list the displacement dofs of the slave /
  *    master interface nodes (any order); a node is an interface node when
@@ -83,6 +86,9 @@ typedef struct {
   const int32_t* lm_node;      /* optional, length n_l                    */
   int32_t n_ns;
   const double* nullspace;     /* optional, n_u * n_ns                    */
+  int32_t device_ptrs;         /* 1: every array above is a device pointer on the
+                                  current GPU (amg_setup only; amg_setup_host
+                                  returns CAMG_ERR_INVALID_ARG)             */
 } amg_problem;
 
 /* Preconditioner options (defaults from amg_default_options). */
@@ -272,6 +278,18 @@ int fgmres_solve(amg_handle* h, int transpose, const double* b, double* x, const
  * the forward solution x and the adjoint solution lam (device FP64, length
  * n).  dK: device FP64, nnz(K).  Asynchronous. */
 int amg_grad_K(amg_handle* h, const double* lam, const double* x, double* dK, void* hip_stream);
+
+/* The same outer product on every block of A = [[K, G], [B, C]]: for the
+ * k-th stored entry (i, j) of a block, in setup order, d[k] = -lam_r[i] *
+ * x_c[j], where lam_r is the row part of lam (lam_u for K and G, lam_l for B
+ * and C) and x_c the column part of x (x_u for K and B, x_l for G and C).
+ * That is dL/dA_ij = -lam_i x_j restricted to A's sparsity pattern, for x
+ * solving A x = b and lam solving A^T lam = dL/dx (the differentiation of
+ * the block system of Sec. 2.3 with respect to its stored entries).
+ * lam, x: device FP64, length n.  dK, dG, dB, dC: device FP64 arrays of the
+ * blocks' nnz; NULL skips a block.  Asynchronous. */
+int amg_grad_A(amg_handle* h, const double* lam, const double* x, double* dK, double* dG, double* dB, double* dC,
+               void* hip_stream);
 
 /* Per-kernel timing with hipEvents around every launch of the selected
  * kernel classes (bit mask of CAMG_KCLASS_*), recorded on the stream the

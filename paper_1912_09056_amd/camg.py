@@ -54,6 +54,7 @@ class amg_problem(Structure):
         ("lm_node", POINTER(c_int32)),
         ("n_ns", c_int32),
         ("nullspace", POINTER(c_double)),
+        ("device_ptrs", c_int32),
     ]
 
 
@@ -148,6 +149,7 @@ SIGNATURES = {
         [c_void_p, c_int, c_void_p, c_void_p, POINTER(amg_gmres_options), POINTER(amg_gmres_result), c_void_p],
     ),
     "amg_grad_K": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "amg_grad_A": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "amg_profile_enable": (c_int, [c_void_p, c_int]),
     "amg_profile_read": (c_int, [c_void_p, c_int, POINTER(c_int64), POINTER(c_double)]),
     "amg_destroy": (None, [c_void_p]),
@@ -278,16 +280,7 @@ class AMGSolver:
 
     def __init__(self, dim, K, G, B, C, slave_dofs, master_dofs, nullspace=None, lm_node=None,
                  options: AMGOptions = None, device=None, host_only: bool = False):
-        self.lib = load_library()
-        self.host_only = host_only
-        if host_only:
-            self.device = None
-        else:
-            self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        self.options = options or AMGOptions()
         n_u, n_l = K.shape[0], C.shape[0]
-        self.n_u, self.n_l, self.n = n_u, n_l, n_u + n_l
-        self.dim = dim
         keep = []
         prob = amg_problem()
         prob.dim = dim
@@ -310,7 +303,21 @@ class AMGSolver:
             keep.append(flat)
             prob.n_ns = ns.shape[1]
             prob.nullspace = _ptr(flat, c_double)
-        self.K_nnz = keep[2].size
+        nnz = {"K": keep[2].size, "G": keep[5].size, "B": keep[8].size, "C": keep[11].size}
+        self._finish(prob, n_u, n_l, dim, nnz, options, device, host_only)
+
+    def _finish(self, prob, n_u, n_l, dim, nnz, options, device, host_only):
+        self.lib = load_library()
+        self.host_only = host_only
+        if host_only:
+            self.device = None
+        else:
+            self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.options = options or AMGOptions()
+        self.n_u, self.n_l, self.n = n_u, n_l, n_u + n_l
+        self.dim = dim
+        self.K_nnz = nnz["K"]
+        self.block_nnz = dict(nnz)
         h = c_void_p()
         opts = self.options.to_c()
         if host_only:
@@ -320,6 +327,55 @@ class AMGSolver:
                 _check(self.lib.amg_setup(byref(prob), byref(opts), _stream_ptr(), byref(h)))
         self.handle = h
         self.n_levels = self.lib.amg_num_levels(h)
+
+    @classmethod
+    def from_device(cls, dim, blocks, slave_dofs, master_dofs, nullspace=None, lm_node=None,
+                    options: AMGOptions = None):
+        """Setup from device-resident arrays (device_ptrs = 1): `blocks` maps
+        "K", "G", "B", "C" to (rowptr int64, col int32, val float64, (nrows,
+        ncols)) with the arrays as CUDA tensors on the current device;
+        slave_dofs / master_dofs / lm_node int32 and nullspace float64
+        (n_u x n_ns, column-major: a tensor of shape (n_ns, n_u)) likewise.
+        The library copies them down to build the hierarchy."""
+        self = cls.__new__(cls)
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def dp(t, dtype, ctype):
+            if t is None or t.numel() == 0:
+                return None, None
+            t = t.to(device=dev, dtype=dtype).contiguous()
+            return t, ctypes.cast(c_void_p(t.data_ptr()), POINTER(ctype))
+
+        keep = []
+        prob = amg_problem()
+        prob.dim = dim
+        nnz = {}
+        for name in ("K", "G", "B", "C"):
+            rp, ci, v, (nr, nc) = blocks[name]
+            trp, prp = dp(rp, torch.int64, c_int64)
+            tci, pci = dp(ci, torch.int32, c_int32)
+            tv, pv = dp(v, torch.float64, c_double)
+            keep += [trp, tci, tv]
+            nnz[name] = 0 if tci is None else tci.numel()
+            setattr(prob, name, amg_csr(nr, nc, nnz[name], prp, pci, pv))
+        tsd, psd = dp(torch.as_tensor(slave_dofs), torch.int32, c_int32)
+        tmd, pmd = dp(torch.as_tensor(master_dofs), torch.int32, c_int32)
+        keep += [tsd, tmd]
+        prob.n_slave = 0 if tsd is None else tsd.numel()
+        prob.n_master = 0 if tmd is None else tmd.numel()
+        prob.slave_dofs, prob.master_dofs = psd, pmd
+        if lm_node is not None:
+            tln, prob.lm_node = dp(torch.as_tensor(lm_node), torch.int32, c_int32)
+            keep.append(tln)
+        if nullspace is not None:
+            tns, prob.nullspace = dp(torch.as_tensor(nullspace), torch.float64, c_double)
+            keep.append(tns)
+            prob.n_ns = tns.shape[0]
+        prob.device_ptrs = 1
+        torch.cuda.synchronize()
+        n_u, n_l = blocks["K"][3][0], blocks["C"][3][0]
+        self._finish(prob, n_u, n_l, dim, nnz, options, dev, False)
+        return self
 
     def __del__(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -404,6 +460,15 @@ class AMGSolver:
         dK = torch.empty(self.K_nnz, dtype=torch.float64, device=self.device)
         _check(self.lib.amg_grad_K(self.handle, _dptr(lam), _dptr(x), _dptr(dK), _stream_ptr(stream)))
         return dK
+
+    def grad_A(self, lam, x, blocks=("K", "G", "B", "C"), stream=None):
+        """{block: -lam_i x_j on that block's stored entries} for the named
+        blocks of A = [[K, G], [B, C]]."""
+        lam, x = self._vec(lam), self._vec(x)
+        out = {name: torch.empty(self.block_nnz[name], dtype=torch.float64, device=self.device) for name in blocks}
+        args = [_dptr(out[name]) if name in out else None for name in ("K", "G", "B", "C")]
+        _check(self.lib.amg_grad_A(self.handle, _dptr(lam), _dptr(x), *args, _stream_ptr(stream)))
+        return out
 
     def update_fine_values(self, K_val=None, G_val=None, B_val=None, C_val=None, stream=None):
         args = []

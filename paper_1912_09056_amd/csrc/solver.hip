@@ -1363,6 +1363,56 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   return h;
 }
 
+// Host copies of a problem statement whose arrays are device pointers
+// (device_ptrs = 1).  The hierarchy is built on the host, so the arrays are
+// copied down once; sizes come from the (host) structure itself.
+struct StagedProblem {
+  amg_problem p{};
+  std::vector<int64_t> rp[4];
+  std::vector<int32_t> ci[4];
+  std::vector<double> v[4];
+  std::vector<int32_t> sd, md, ln;
+  std::vector<double> ns;
+};
+
+template <typename T>
+static void stage_array(std::vector<T>& dst, const T* src, int64_t count, const char* what) {
+  if (count < 0) api_fail(CAMG_ERR_SHAPE, std::string(what) + ": negative length");
+  dst.resize((size_t)count);
+  if (count == 0) return;
+  if (!src) api_fail(CAMG_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  CAMG_HIP(hipMemcpy(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost));
+}
+
+static void stage_problem(const amg_problem& in, StagedProblem& out) {
+  out.p = in;
+  out.p.device_ptrs = 0;
+  amg_csr* blocks[4] = {&out.p.K, &out.p.G, &out.p.B, &out.p.C};
+  const char* names[4] = {"K", "G", "B", "C"};
+  for (int b = 0; b < 4; ++b) {
+    amg_csr& A = *blocks[b];
+    if (A.nrows < 0 || A.nnz < 0 || A.nnz >= (int64_t(1) << 31)) api_fail(CAMG_ERR_SHAPE, std::string(names[b]) + ": sizes");
+    stage_array(out.rp[b], A.rowptr, A.nrows + 1, names[b]);
+    stage_array(out.ci[b], A.col, A.nnz, names[b]);
+    stage_array(out.v[b], A.val, A.nnz, names[b]);
+    A.rowptr = out.rp[b].data();
+    A.col = A.nnz ? out.ci[b].data() : nullptr;
+    A.val = A.nnz ? out.v[b].data() : nullptr;
+  }
+  stage_array(out.sd, in.slave_dofs, in.n_slave, "slave_dofs");
+  stage_array(out.md, in.master_dofs, in.n_master, "master_dofs");
+  out.p.slave_dofs = in.n_slave ? out.sd.data() : nullptr;
+  out.p.master_dofs = in.n_master ? out.md.data() : nullptr;
+  if (in.lm_node) {
+    stage_array(out.ln, in.lm_node, in.C.nrows, "lm_node");
+    out.p.lm_node = out.ln.data();
+  }
+  if (in.nullspace && in.n_ns > 0) {
+    stage_array(out.ns, in.nullspace, in.K.nrows * (int64_t)in.n_ns, "nullspace");
+    out.p.nullspace = out.ns.data();
+  }
+}
+
 static void need_device(const amg_handle* h) {
   if (h->lev.empty()) api_fail(CAMG_ERR_INVALID_ARG, "handle was built by amg_setup_host and has no device data");
 }
@@ -1376,6 +1426,12 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
     if (!out) api_fail(CAMG_ERR_INVALID_ARG, "NULL output handle");
     *out = nullptr;
     PhaseTimer pt_all("amg_setup total");
+    StagedProblem staged;
+    if (p && p->device_ptrs) {
+      PhaseTimer pt("device-to-host staging");
+      stage_problem(*p, staged);
+      p = &staged.p;
+    }
     auto h = [&] {
       PhaseTimer pt("host import + hierarchy");
       return build_host(p, opts);
@@ -1401,6 +1457,7 @@ int amg_setup_host(const amg_problem* p, const amg_options* opts, amg_handle** o
   return guarded([&]() -> int {
     if (!out) api_fail(CAMG_ERR_INVALID_ARG, "NULL output handle");
     *out = nullptr;
+    if (p && p->device_ptrs) api_fail(CAMG_ERR_INVALID_ARG, "amg_setup_host takes host pointers only");
     *out = build_host(p, opts).release();
     return CAMG_OK;
   });
@@ -1565,6 +1622,24 @@ int amg_grad_K(amg_handle* h, const double* lam, const double* x, double* dK, vo
     need_device(h);
     CAMG_HIP(hipSetDevice(h->device));
     grad_K(h->lev[0].K.view<double>(), lam, x, dK, as_stream(stream));
+    return CAMG_OK;
+  });
+}
+
+int amg_grad_A(amg_handle* h, const double* lam, const double* x, double* dK, double* dG, double* dB, double* dC,
+               void* stream) {
+  return guarded([&]() -> int {
+    if (!h || !lam || !x) api_fail(CAMG_ERR_INVALID_ARG, "NULL argument");
+    need_device(h);
+    CAMG_HIP(hipSetDevice(h->device));
+    const DevLevel& D = h->lev[0];
+    const int64_t nu = D.n_u;
+    hipStream_t s = as_stream(stream);
+    // block (rows, columns) = (u, u), (u, l), (l, u), (l, l) of [u; l]
+    if (dK) grad_K(D.K.view<double>(), lam, x, dK, s);
+    if (dG) grad_K(D.G.view<double>(), lam, x + nu, dG, s);
+    if (dB) grad_K(D.B.view<double>(), lam + nu, x, dB, s);
+    if (dC) grad_K(D.C.view<double>(), lam + nu, x + nu, dC, s);
     return CAMG_OK;
   });
 }
