@@ -49,6 +49,7 @@ extern "C" {
 #define CAMG_ERR_HIP (-7)              /* HIP runtime error                    */
 #define CAMG_ERR_OOM (-8)              /* device or host allocation failed     */
 #define CAMG_ERR_UNMAPPED_MULTIPLIER (-9) /* multiplier coupled to no slave dof */
+#define CAMG_ERR_TOO_LARGE (-10)       /* V-cycle work vectors exceed the no-allocation scratch */
 
 typedef struct amg_handle amg_handle;
 
@@ -265,6 +266,23 @@ int amg_apply_operator(amg_handle* h, int transpose, const double* x, double* y,
  * forward cycle (adjoint sweeps, pre/post counts swapped, A_c^-T).  Device
  * FP64 vectors of length n; r and z must not overlap.  Asynchronous. */
 int amg_vcycle_apply(amg_handle* h, int transpose, const double* r, double* z, void* hip_stream);
+
+/* The V-cycle of amg_vcycle_apply for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels in the same order and the same result,
+ * but it allocates nothing, captures no graph and times no kernel.  Its work
+ * vectors (every level's right-hand side, iterates, residual, multiplier
+ * increments and prediction buffers, in the precision of the hierarchy)
+ * live in a fixed array of CAMG_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * library's first amg_setup on that GPU until the process ends; the call
+ * clears it with a fill kernel first (no memset node).  Problems whose work
+ * vectors do not fit return CAMG_ERR_TOO_LARGE before anything is launched
+ * (about 1.1M unknowns in FP64, 2.2M in mixed precision).  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (other streams, other
+ * handles, other threads) race.  r, z: device FP64, length n, not
+ * overlapping.  Asynchronous. */
+#define CAMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int amg_vcycle_apply_noalloc(amg_handle* h, int transpose, const double* r, double* z, void* hip_stream);
 
 /* Right-preconditioned flexible GMRES(m) with CGS2 and Givens rotations,
  * one V-cycle per iteration (Sec. 3), on A (transpose = 0) or A^T.

@@ -144,6 +144,7 @@ SIGNATURES = {
     "amg_update_fine_values": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "amg_apply_operator": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "amg_vcycle_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "amg_vcycle_apply_noalloc": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "fgmres_solve": (
         c_int,
         [c_void_p, c_int, c_void_p, c_void_p, POINTER(amg_gmres_options), POINTER(amg_gmres_result), c_void_p],
@@ -439,6 +440,13 @@ class AMGSolver:
         r = self._vec(r)
         z = torch.empty_like(r)
         _check(self.lib.amg_vcycle_apply(self.handle, int(transpose), _dptr(r), _dptr(z), _stream_ptr(stream)))
+        return z
+
+    def vcycle_noalloc(self, r, z, transpose=False, stream=None):
+        """z = M^-1 r (or M^-T r) through the allocation-free entry point;
+        r and z are caller-owned FP64 device vectors of length n."""
+        _check(self.lib.amg_vcycle_apply_noalloc(self.handle, int(transpose), _dptr(r), _dptr(z),
+                                                 _stream_ptr(stream)))
         return z
 
     def solve(self, b, x0=None, transpose=False, m=50, rtol=1e-8, max_iters=1000, fixed_iters=0, lookahead=1,

@@ -12,7 +12,10 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/camg.h"
@@ -393,6 +396,36 @@ struct ProfScope {
 
 using namespace camg;
 
+// Work memory of amg_vcycle_apply_noalloc: the V-cycle vectors of every level
+// (right-hand side, iterates, residual, multiplier increments, prediction
+// buffers) for callers that cannot allocate.  Each GPU that runs the library
+// holds one copy until the process ends; host code reaches it only through
+// the per-device address from hipGetSymbolAddress, never through this name.
+static constexpr size_t kNoallocScratchBytes = CAMG_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace camg {
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current; looked up
+// once per device.
+static void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) api_fail(CAMG_ERR_INVALID_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    CAMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) api_fail(CAMG_ERR_HIP, "no device address for the no-allocation scratch array");
+    g_scratch_addr[device] = p;
+  }
+  return g_scratch_addr[device];
+}
+
+}  // namespace camg
+
 struct amg_handle {
   int device = 0;
   amg_options opts{};
@@ -418,6 +451,7 @@ struct amg_handle {
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   void* vout[2] = {nullptr, nullptr};
   Prof prof;
+  void* scratch = nullptr;  // this device's no-allocation scratch array (device address)
   ~amg_handle() {
     for (int t = 0; t < 2; ++t) {
       if (vexec[t]) (void)hipGraphExecDestroy(vexec[t]);
@@ -990,6 +1024,69 @@ static void precondition(amg_handle& h, bool transpose, const double* r, double*
   vcycle_to(h, transpose, z, s);
 }
 
+// The work vectors of one level, in the order they are laid out in scratch.
+template <typename T>
+static std::vector<std::pair<DBuf<T>*, int64_t>> work_vectors(DevLevel& D) {
+  LevelVecs<T>& V = vecs<T>(D);
+  const int64_t n = D.n(), nu = std::max<int64_t>(D.n_u, 1), nl = std::max<int64_t>(D.n_l, 1);
+  return {{&V.b, n},      {&V.z, n},       {&V.zn, n},     {&V.r, n},    {&V.delta, nl},
+          {&V.delta2, nl}, {&V.qrhs, nl},   {&V.aux1, nu},  {&V.aux2, nu}, {&V.su, nu}};
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Bytes of scratch that one V-cycle of this handle needs.
+template <typename T>
+static size_t noalloc_bytes(amg_handle& h) {
+  size_t total = 0;
+  for (DevLevel& D : h.lev)
+    for (auto& wv : work_vectors<T>(D)) total += align256((size_t)wv.second * sizeof(T));
+  return total;
+}
+
+// One eager V-cycle whose work vectors live in this device's scratch array:
+// the level buffers of the handle are pointed at carve-outs of it for the
+// duration of the launches (restored on every exit path), the carved region
+// is cleared first with a fill kernel, and neither graph capture nor event
+// profiling runs, so nothing is allocated.  The kernels are the ones of
+// amg_vcycle_apply in the same order.
+template <typename T>
+static void vcycle_noalloc(amg_handle& h, bool transpose, const double* r, double* z, hipStream_t s) {
+  const size_t need = noalloc_bytes<T>(h);
+  if (need > kNoallocScratchBytes)
+    api_fail(CAMG_ERR_TOO_LARGE, "V-cycle work vectors need " + std::to_string(need) +
+                                     " bytes; the no-allocation scratch holds " +
+                                     std::to_string(kNoallocScratchBytes));
+  struct Restore {
+    std::vector<std::pair<DBuf<T>*, T*>> saved;
+    Prof& prof;
+    int mask;
+    ~Restore() {
+      for (auto& sv : saved) sv.first->p = sv.second;
+      prof.mask = mask;
+    }
+  } restore{{}, h.prof, h.prof.mask};
+  h.prof.mask = 0;
+  unsigned char* base = static_cast<unsigned char*>(h.scratch);
+  size_t off = 0;
+  for (DevLevel& D : h.lev)
+    for (auto& wv : work_vectors<T>(D)) {
+      restore.saved.emplace_back(wv.first, wv.first->p);
+      wv.first->p = reinterpret_cast<T*>(base + off);
+      off += align256((size_t)wv.second * sizeof(T));
+    }
+  zero_vec<float>(reinterpret_cast<float*>(base), (int64_t)(off / sizeof(float)), s);
+  const int64_t n = h.lev[0].n();
+  LevelVecs<T>& V0 = vecs<T>(h.lev[0]);
+  if constexpr (std::is_same<T, float>::value) {
+    cast_d2f(r, V0.b.p, n, s);
+    cast_f2d(vcycle_level<float>(h, 0, transpose, s), z, n, s);
+  } else {
+    copy_vec<double>(r, V0.b.p, n, s);
+    copy_vec<double>(vcycle_level<double>(h, 0, transpose, s), z, n, s);
+  }
+}
+
 // Runs the V-cycle on the level-0 input already in vecs(0).b and writes the
 // FP64 result to z.
 // y = A x, or y = b - A x when b is given (FP64 level-0 operator).
@@ -1438,6 +1535,7 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
     }();
     hipStream_t s = as_stream(stream);
     CAMG_HIP(hipGetDevice(&h->device));
+    h->scratch = scratch_address(h->device);
     CAMG_HIP(hipEventCreate(&h->ev0));
     CAMG_HIP(hipEventCreate(&h->ev1));
     CAMG_HIP(hipHostMalloc((void**)&h->hbuf, (4 + 4 * amg_handle::kSlots) * sizeof(double),
@@ -1600,6 +1698,19 @@ int amg_vcycle_apply(amg_handle* h, int transpose, const double* r, double* z, v
   });
 }
 
+int amg_vcycle_apply_noalloc(amg_handle* h, int transpose, const double* r, double* z, void* stream) {
+  return guarded([&]() -> int {
+    if (!h || !r || !z) api_fail(CAMG_ERR_INVALID_ARG, "NULL argument");
+    if (r == z) api_fail(CAMG_ERR_INVALID_ARG, "r and z must not overlap");
+    need_device(h);
+    if (!h->scratch) api_fail(CAMG_ERR_INVALID_ARG, "handle has no scratch address");
+    CAMG_HIP(hipSetDevice(h->device));
+    if (h->opts.precision == CAMG_PREC_MIXED) vcycle_noalloc<float>(*h, transpose != 0, r, z, as_stream(stream));
+    else vcycle_noalloc<double>(*h, transpose != 0, r, z, as_stream(stream));
+    return CAMG_OK;
+  });
+}
+
 int fgmres_solve(amg_handle* h, int transpose, const double* b, double* x, const amg_gmres_options* gopts,
                  amg_gmres_result* res, void* stream) {
   return guarded([&]() -> int {
@@ -1684,6 +1795,7 @@ const char* amg_strerror(int code) {
     case CAMG_ERR_HIP: return "HIP error";
     case CAMG_ERR_OOM: return "out of memory";
     case CAMG_ERR_UNMAPPED_MULTIPLIER: return "multiplier without slave coupling";
+    case CAMG_ERR_TOO_LARGE: return "problem exceeds the no-allocation scratch";
     default: return "unknown status";
   }
 }
