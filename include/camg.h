@@ -309,6 +309,19 @@ int amg_grad_K(amg_handle* h, const double* lam, const double* x, double* dK, vo
 int amg_grad_A(amg_handle* h, const double* lam, const double* x, double* dK, double* dG, double* dB, double* dC,
                void* hip_stream);
 
+/* Explicit inverse of a dense n x n FP64 matrix on the device: the
+ * factorisation behind the coarsest-level direct solve (the coarse blocks
+ * merged and factorised by LU, weak-scaling solver settings of Sec. 6.2),
+ * which amg_setup runs on the merged coarsest matrix.  Blocked LU with
+ * partial pivoting (largest magnitude, first row on ties) on 64-column
+ * panels, then L U X = P by blocked substitution; every rank-64 update runs
+ * on the FP64 matrix cores.  A, Ainv: device, row-major n x n, not
+ * overlapping; 1 <= n <= 46000.  A pivot not above 1e-13 max |A_ij| returns
+ * CAMG_ERR_SINGULAR_COARSE (Ainv undefined), a non-finite entry
+ * CAMG_ERR_NONFINITE.  Allocates a workspace of two (n rounded up to 64)^2
+ * FP64 matrices; synchronises hip_stream. */
+int amg_dense_inverse(const double* A, double* Ainv, int64_t n, void* hip_stream);
+
 /* Per-kernel timing with hipEvents around every launch of the selected
  * kernel classes (bit mask of CAMG_KCLASS_*), recorded on the stream the
  * kernel runs on.  amg_profile_read synchronises and returns the number of

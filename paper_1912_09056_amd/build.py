@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build", "camg")
 LIB = os.path.join(PKG, "libcamg.so")
 
-SOURCES = ["setup.cpp", "kernels.hip", "solver.hip"]
+SOURCES = ["setup.cpp", "kernels.hip", "dense_inverse.hip", "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -151,6 +151,7 @@ SIGNATURES = {
     ),
     "amg_grad_K": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "amg_grad_A": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "amg_dense_inverse": (c_int, [c_void_p, c_void_p, c_int64, c_void_p]),
     "amg_profile_enable": (c_int, [c_void_p, c_int]),
     "amg_profile_read": (c_int, [c_void_p, c_int, POINTER(c_int64), POINTER(c_double)]),
     "amg_destroy": (None, [c_void_p]),
@@ -375,7 +376,7 @@ class AMGSolver:
         prob.device_ptrs = 1
         torch.cuda.synchronize()
         n_u, n_l = blocks["K"][3][0], blocks["C"][3][0]
-        self._finish(prob, n_u, n_l, dim, nnz, options, dev, False)
+        self._finish(prob, n_u, n_l, dim, nnz, options, dev.index, False)
         return self
 
     def __del__(self):
@@ -499,6 +500,17 @@ class AMGSolver:
         n, ms = c_int64(), c_double()
         _check(self.lib.amg_profile_read(self.handle, kclass, byref(n), byref(ms)))
         return n.value, ms.value
+
+
+def dense_inverse(A: torch.Tensor, stream=None) -> torch.Tensor:
+    """A^-1 of a dense square FP64 CUDA matrix by the library's device LU
+    (amg_dense_inverse)."""
+    lib = load_library()
+    A = A.to(dtype=torch.float64).contiguous()
+    assert A.is_cuda and A.dim() == 2 and A.shape[0] == A.shape[1]
+    out = torch.empty_like(A)
+    _check(lib.amg_dense_inverse(_dptr(A), _dptr(out), A.shape[0], _stream_ptr(stream)))
+    return out
 
 
 def exported_symbols():

@@ -752,9 +752,11 @@ void smoother_data(HostLevel& L, const SetupOptions& opt) {
 
 // Dense LU with partial pivoting (largest magnitude, first index on ties)
 // of the merged coarsest matrix, then its explicit inverse.
-void coarse_inverse(HostLevel& L) {
+// The coarsest level's blocks merged into one dense row-major matrix, and
+// its largest entry magnitude.
+static double merge_dense(const HostLevel& L, std::vector<double>& A) {
   const int64_t nu = L.n_u(), n = L.n();
-  std::vector<double> A((size_t)(n * n), 0.0);
+  A.assign((size_t)(n * n), 0.0);
   auto put = [&](const HostCSR& M, int64_t r0, int64_t c0) {
     for (int64_t i = 0; i < M.nrows; ++i)
       for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) A[(size_t)((r0 + i) * n + c0 + M.ci[k])] += M.v[k];
@@ -765,6 +767,13 @@ void coarse_inverse(HostLevel& L) {
   put(L.C, nu, nu);
   double amax = 0.0;
   for (double a : A) amax = std::max(amax, std::fabs(a));
+  return amax;
+}
+
+void coarse_inverse(HostLevel& L) {
+  const int64_t n = L.n();
+  std::vector<double> A;
+  const double amax = merge_dense(L, A);
   std::vector<int64_t> piv((size_t)n);
   for (int64_t k = 0; k < n; ++k) {
     int64_t p = k;
@@ -909,7 +918,14 @@ void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt) {
     for (size_t l = 0; l < n_smooth; ++l) smoother_data(levels[l], opt);
   }
   PhaseTimer pt("coarsest inverse");
-  if (!opt.simple_coarse) coarse_inverse(levels.back());
+  if (!opt.simple_coarse) {
+    if (opt.device_inverse) {
+      HostLevel& C = levels.back();
+      C.Adense_amax = merge_dense(C, C.Adense);
+    } else {
+      coarse_inverse(levels.back());
+    }
+  }
 }
 
 }  // namespace camg

@@ -119,6 +119,8 @@ struct HostLevel {
   std::vector<double> ablk_inv;    // nodal lumping option: inverse blocks, bs_u x bs_u row-major each
   HostCSR S;                       // B Atilde^-1 G - C (only when relaxed by Jacobi sweeps)
   std::vector<double> Ainv;        // coarsest level with the direct solve: dense inverse, row-major
+  std::vector<double> Adense;      // ... or the merged dense matrix (row-major), inverted on the device
+  double Adense_amax = 0.0;        // max |entry| of Adense (singularity threshold)
   int64_t n_u() const { return K.nrows; }
   int64_t n_l() const { return C.nrows; }
   int64_t n() const { return n_u() + n_l(); }
@@ -135,6 +137,7 @@ struct SetupOptions {
   int schur = 0;         // 0 diagonal of S, 1 signed l1 row sums of S, 2 nodal blocks of S
   int schur_sweeps = 1;  // > 1: keep S for Jacobi sweeps
   bool simple_coarse = false;  // coarsest level smooths (smoother data, no dense inverse)
+  bool device_inverse = false; // coarsest level: keep the merged matrix for the device LU (no host LU)
   // Braess-Sarazin: > 0 scales the lumping to lumping * bs_alpha, which then
   // also serves as the prediction's diagonal (the sweep runs with unit dampings)
   double bs_alpha = 0.0;

@@ -20,6 +20,7 @@
 
 #include "../../include/camg.h"
 #include "common.hpp"
+#include "dense_inverse.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
 
@@ -528,12 +529,21 @@ static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool dense_coarse, h
     up(V.sdinv, H.sd_inv);
     if (!H.sblk_inv.empty()) up(V.sblk, H.sblk_inv);
     if (!H.ablk_inv.empty()) up(V.ablk, H.ablk_inv);
-  } else {
+  } else if (!H.Ainv.empty()) {
     up(V.Ainv, H.Ainv);
     std::vector<double> t(H.Ainv.size());
     for (int64_t i = 0; i < n; ++i)
       for (int64_t j = 0; j < n; ++j) t[(size_t)(j * n + i)] = H.Ainv[(size_t)(i * n + j)];
     up(V.AinvT, t);
+  } else {
+    // LU of the merged matrix on the device (FP64), the inverse and its
+    // transpose rounded to T
+    DBuf<double> a;
+    a.upload(H.Adense, s);
+    V.Ainv.alloc((size_t)(n * n));
+    V.AinvT.alloc((size_t)(n * n));
+    if (!dense_inverse<T>(a.p, n, 1e-13 * H.Adense_amax, V.Ainv.p, V.AinvT.p, s))
+      throw SetupError{CAMG_ERR_SINGULAR_COARSE, "coarsest merged matrix is singular"};
   }
 }
 
@@ -1371,7 +1381,9 @@ void amg_default_gmres_options(amg_gmres_options* o) {
 
 namespace camg {
 
-static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_options* opts) {
+// device_inverse: keep the coarsest merged matrix for the device LU
+// (amg_setup) instead of factorising it on the host (amg_setup_host).
+static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_options* opts, bool device_inverse) {
   if (!p) api_fail(CAMG_ERR_INVALID_ARG, "NULL problem");
   amg_options o;
   amg_default_options(&o);
@@ -1456,6 +1468,7 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   so.schur_sweeps = o.schur_sweeps;
   so.simple_coarse = o.coarse_solver == CAMG_COARSE_SIMPLE;
   so.bs_alpha = o.smoother == CAMG_SMOOTHER_BRAESS_SARAZIN ? o.simple_alpha : 0.0;
+  so.device_inverse = device_inverse;
   build_hierarchy(h->host, so);
   return h;
 }
@@ -1531,7 +1544,7 @@ int amg_setup(const amg_problem* p, const amg_options* opts, void* stream, amg_h
     }
     auto h = [&] {
       PhaseTimer pt("host import + hierarchy");
-      return build_host(p, opts);
+      return build_host(p, opts, true);
     }();
     hipStream_t s = as_stream(stream);
     CAMG_HIP(hipGetDevice(&h->device));
@@ -1556,7 +1569,7 @@ int amg_setup_host(const amg_problem* p, const amg_options* opts, amg_handle** o
     if (!out) api_fail(CAMG_ERR_INVALID_ARG, "NULL output handle");
     *out = nullptr;
     if (p && p->device_ptrs) api_fail(CAMG_ERR_INVALID_ARG, "amg_setup_host takes host pointers only");
-    *out = build_host(p, opts).release();
+    *out = build_host(p, opts, false).release();
     return CAMG_OK;
   });
 }
@@ -1733,6 +1746,25 @@ int amg_grad_K(amg_handle* h, const double* lam, const double* x, double* dK, vo
     need_device(h);
     CAMG_HIP(hipSetDevice(h->device));
     grad_K(h->lev[0].K.view<double>(), lam, x, dK, as_stream(stream));
+    return CAMG_OK;
+  });
+}
+
+int amg_dense_inverse(const double* A, double* Ainv, int64_t n, void* stream) {
+  return guarded([&]() -> int {
+    if (!A || !Ainv || n <= 0) api_fail(CAMG_ERR_INVALID_ARG, "NULL argument or n <= 0");
+    if (A == Ainv) api_fail(CAMG_ERR_INVALID_ARG, "A and Ainv must not overlap");
+    if (n > 46000) api_fail(CAMG_ERR_INVALID_ARG, "n too large for the dense inverse");
+    hipStream_t s = as_stream(stream);
+    // the singularity threshold of the coarsest solve: 1e-13 max |A_ij|
+    DBuf<double> amax(1);
+    max_abs(A, n * n, amax.p, s);
+    double am = 0.0;
+    CAMG_HIP(hipMemcpyAsync(&am, amax.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    CAMG_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(am)) api_fail(CAMG_ERR_NONFINITE, "non-finite matrix entry");
+    if (!dense_inverse<double>(A, n, 1e-13 * am, Ainv, nullptr, s))
+      api_fail(CAMG_ERR_SINGULAR_COARSE, "matrix is singular (pivot below 1e-13 max|A_ij|)");
     return CAMG_OK;
   });
 }
