@@ -61,15 +61,16 @@ def smooth_u_bytes(info0, nnz_K_true, elem):
     Both count G's entries (value + column) and row pointers, K's row
     pointers, and the vectors b_u, jinv, z_u (read once), z_l and zn_u
     (written).  Blocked layout: `algorithmic` counts K's true nonzeros
-    (one value each) plus one 4-byte index per nonzero bs x bs block;
+    (one value each) plus one block-column index (2 or 4 bytes, as stored)
+    per nonzero bs x bs block;
     `stored` counts every value of those blocks (including the zeros a block
     holds) and is what the kernel actually streams (slice padding is in
     neither).  CSR layout: K's entries (value + column), both the same."""
     n_u, n_l = info0["n_u"], info0["n_l"]
     vec = n_u * elem * 4 + n_l * elem + info0["nnz_G"] * (elem + 4) + (n_u + 1) * 4
     if info0["k_layout"] == 1:
-        bs = info0["k_bs"]
-        return nnz_K_true * elem + info0["k_blocks"] * 4 + vec, info0["k_blocks"] * (bs * bs * elem + 4) + vec
+        bs, ib = info0["k_bs"], info0["k_index_bytes"]
+        return nnz_K_true * elem + info0["k_blocks"] * ib + vec, info0["k_blocks"] * (bs * bs * elem + ib) + vec
     b = info0["nnz_K"] * (elem + 4) + (n_u + 1) * 4 + vec
     return b, b
 
@@ -81,7 +82,7 @@ def vcycle_matrix_bytes(solver, elem):
     sweep but the first from zero, its extra Jacobi steps, and the residual
     before restriction); G twice per sweep plus the residual; B and C once
     per sweep plus the residual; R and P once.  K in its device layout
-    (bs x bs blocks with a 4-byte block index, or CSR), P and R either CSR or
+    (bs x bs blocks with a 2- or 4-byte block index, or CSR), P and R either CSR or
     index-free (values plus one 4-byte base column per fine row for P, one
     4-byte row index per fine row for R), the other blocks CSR (value +
     4-byte column).  The coarsest level: its dense inverse."""
@@ -96,7 +97,7 @@ def vcycle_matrix_bytes(solver, elem):
             total += n * n * elem
             break
         if info["k_layout"] in (1, 2):
-            kb = info["k_blocks"] * (info["k_bs"] ** 2 * elem + 4)
+            kb = info["k_blocks"] * (info["k_bs"] ** 2 * elem + info["k_index_bytes"])
         else:
             kb = info["nnz_K"] * (elem + 4)
         e = elem + 4
@@ -319,8 +320,9 @@ def main():
             "traffic": traffic,
             "achieved_from_counters_GBps": traffic / avg_s / 1e9 if traffic else None,
             "bytes_per_launch": bytes_alg,
-            "bytes_model": "K's true nonzeros (one FP32 value each) + one 4-byte index per nonzero 3x3 block + G "
-                           "CSR + row pointers + 5 FP32 vectors of n_u, read or written once",
+            "bytes_model": f"K's true nonzeros (one FP32 value each) + one {info0['k_index_bytes']}-byte block-column "
+                           "index per nonzero 3x3 block + G CSR + row pointers + 5 FP32 vectors of n_u, read or "
+                           "written once",
             "bytes_per_launch_stored": bytes_stored,
             "frac_stored_bytes": bytes_stored / avg_s / 1e9 / peak,
             "stored_bytes_model": "as bytes_model but every value of each nonzero 3x3 block (the zeros a block "

@@ -212,6 +212,9 @@ typedef struct {
   int32_t transfer_layout; /* P and R on device: 0 CSR, 1 tentative aggregate pattern without column
                               indices (per-row base column, dense row values, per-aggregate row lists);
                               -1 on the coarsest level or a host-only handle */
+  int32_t k_index_bytes;  /* bytes per stored block-column index of the blocked layouts: 2 when the
+                             columns are kept as 16-bit deltas from the row's node, else 4 (0: CSR
+                             or host-only) */
 } amg_level_info;
 
 void amg_default_options(amg_options* opts);

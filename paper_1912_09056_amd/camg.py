@@ -124,6 +124,7 @@ class amg_level_info(Structure):
         ("k_blocks", c_int64),
         ("k_slots", c_int64),
         ("transfer_layout", c_int32),
+        ("k_index_bytes", c_int32),
     ]
 
 

@@ -100,11 +100,17 @@ struct DCSR {
 //   bcol[p * 64 + lane]                       block column of node 64 s + lane
 //   val[(p * bs * bs + a * bs + b) * 64 + lane] entry (a, b) of that block
 // Short rows are padded with zero blocks pointing at a valid node.
+// When every block column lies within +-32767 nodes of its row's node (a
+// banded node numbering, as on structured meshes), bdel replaces bcol:
+//   bdel[p * 64 + lane] = block column - (64 s + lane),
+// two bytes per block instead of four.
 template <typename T>
 struct DBELL {
   int32_t n_nodes = 0, bs = 0, n_slices = 0;
+  int32_t stream = 0;  // 1: load the values nontemporally (they are read once per pass)
   const int32_t* slice_ptr = nullptr;
   const int32_t* bcol = nullptr;
+  const int16_t* bdel = nullptr;
   const T* val = nullptr;
 };
 

@@ -643,13 +643,19 @@ __global__ void __launch_bounds__(kBlock) k_cgs_finish(const double* __restrict_
     const double gj = g[j];
     g[j + 1] = -sv * gj;
     g[j] = c * gj;
+    // norm of the Hessenberg column (= ||A z_j|| in exact arithmetic; the
+    // rotations keep it): the scale of the relative breakdown test
+    double cn2 = 0.0;
+    for (int i = 0; i <= j; ++i) cn2 += col[i] * col[i];
     res[0] = fabs(g[j + 1]);
     res[1] = hn;
     res[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+    res[3] = sqrt(cn2);
     if (res_host) {  // the host's copy (pinned memory), read after the step's event
       res_host[0] = res[0];
       res_host[1] = res[1];
       res_host[2] = res[2];
+      res_host[3] = res[3];
     }
   }
   __syncthreads();
@@ -675,38 +681,71 @@ __global__ void __launch_bounds__(kBlock) k_arnoldi_prep(const double* __restric
 
 // ---- sliced blocked-ELL kernels ---------------------------------------------
 
-// Row (node 64*slice + lane, component a) of a BELL matrix times x.  BS > 0
-// is the compile-time block size; BS == 0 reads it at run time.
-// A blocked-ELL value, read once per launch.  FP64 values are loaded
+// A blocked-ELL value, read once per launch.  FP64 values are always loaded
 // nontemporally: they are 8/9 of an FP64 pass's bytes, and streaming them
-// past the caches leaves the x-gathers and, in the mixed solve, the FP32
-// level-0 copy of K (152 MB on the 40^3 workload, which fits the 256 MB
-// last-level cache) resident across the FP64 operator applies.  FP32 values
-// load normally (nontemporal was 2 % slower there).
-template <typename T>
+// past the caches leaves the x-gathers and, in the mixed solve, a small FP32
+// level-0 copy of K resident in the 256 MB last-level cache across the FP64
+// operator applies.  FP32 values stream nontemporally too when the matrix
+// cannot stay in that cache anyway (A.stream, set at upload); below that
+// they load normally and are reused from it across the cycle's passes
+// (nontemporal FP32 loads were 2 % slower on the 40^3 workload's 152 MB K,
+// 4 % faster on the 100^3 workload's 2.3 GB).
+template <typename T, bool NT>
 __device__ __forceinline__ T bell_val(const T* p) {
-  if constexpr (sizeof(T) == 8) return __builtin_nontemporal_load(p);
+  if constexpr (NT) return __builtin_nontemporal_load(p);
   else return *p;
+}
+
+// Block column of position p for lane `lane` of slice `slice`: a 16-bit
+// delta from the lane's node (DEL) or the full index.
+// base: the lane's node, or 0 for the lanes past the last node (their
+// deltas are 0, so they gather x[0] like the padded full indices do).
+template <typename T, bool DEL>
+__device__ __forceinline__ int bell_col(const DBELL<T>& A, int64_t p, int base, int lane) {
+  if constexpr (DEL) return base + (int)A.bdel[p * 64 + lane];
+  else return A.bcol[p * 64 + lane];
+}
+
+// Row (node 64*slice + lane, component a) of a BELL matrix times x (x
+// converted to T on load).  BS > 0 is the compile-time block size; BS == 0
+// reads it at run time.  DEL: 16-bit column deltas; NT: nontemporal value
+// loads (both chosen per matrix outside the loop, so each loop has one kind
+// of load).
+template <typename T, typename XT, int BS, bool DEL, bool NT>
+__device__ __forceinline__ T bell_row_impl(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
+  const int bs = BS > 0 ? BS : A.bs;
+  const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
+  const int node = slice * 64 + lane;
+  const int base = node < A.n_nodes ? node : 0;
+  T acc = T(0);
+#pragma unroll 4
+  for (int p = p0; p < p1; ++p) {
+    const int c = bell_col<T, DEL>(A, p, base, lane);
+    const T* __restrict__ v = A.val + ((int64_t)p * (bs * bs) + a * bs) * 64 + lane;
+    const XT* __restrict__ xc = x + (int64_t)c * bs;
+    if (BS > 0) {
+#pragma unroll
+      for (int b = 0; b < BS; ++b) acc += bell_val<T, NT>(v + b * 64) * (T)xc[b];
+    } else {
+      for (int b = 0; b < bs; ++b) acc += bell_val<T, NT>(v + b * 64) * (T)xc[b];
+    }
+  }
+  return acc;
+}
+
+template <typename T, typename XT, int BS>
+__device__ __forceinline__ T bell_row_any(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
+  if (A.bdel) {
+    if (A.stream) return bell_row_impl<T, XT, BS, true, true>(A, x, slice, lane, a);
+    return bell_row_impl<T, XT, BS, true, false>(A, x, slice, lane, a);
+  }
+  if (A.stream) return bell_row_impl<T, XT, BS, false, true>(A, x, slice, lane, a);
+  return bell_row_impl<T, XT, BS, false, false>(A, x, slice, lane, a);
 }
 
 template <typename T, int BS>
 __device__ __forceinline__ T bell_row(const DBELL<T>& A, const T* __restrict__ x, int slice, int lane, int a) {
-  const int bs = BS > 0 ? BS : A.bs;
-  const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
-  T acc = T(0);
-#pragma unroll 4
-  for (int p = p0; p < p1; ++p) {
-    const int c = A.bcol[(int64_t)p * 64 + lane];
-    const T* __restrict__ v = A.val + ((int64_t)p * (bs * bs) + a * bs) * 64 + lane;
-    const T* __restrict__ xc = x + (int64_t)c * bs;
-    if (BS > 0) {
-#pragma unroll
-      for (int b = 0; b < BS; ++b) acc += bell_val(v + b * 64) * xc[b];
-    } else {
-      for (int b = 0; b < bs; ++b) acc += bell_val(v + b * 64) * xc[b];
-    }
-  }
-  return acc;
+  return bell_row_any<T, T, BS>(A, x, slice, lane, a);
 }
 
 // XCD-aware slice order for the blocked-ELL kernels: the dispatcher hands
@@ -725,22 +764,7 @@ __device__ __forceinline__ int xcd_slice(int g, int n) {
 // load).
 template <typename T, typename XT, int BS>
 __device__ __forceinline__ T bell_row_x(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
-  const int bs = BS > 0 ? BS : A.bs;
-  const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
-  T acc = T(0);
-#pragma unroll 4
-  for (int p = p0; p < p1; ++p) {
-    const int c = A.bcol[(int64_t)p * 64 + lane];
-    const T* __restrict__ v = A.val + ((int64_t)p * (bs * bs) + a * bs) * 64 + lane;
-    const XT* __restrict__ xc = x + (int64_t)c * bs;
-    if (BS > 0) {
-#pragma unroll
-      for (int b = 0; b < BS; ++b) acc += bell_val(v + b * 64) * (T)xc[b];
-    } else {
-      for (int b = 0; b < bs; ++b) acc += bell_val(v + b * 64) * (T)xc[b];
-    }
-  }
-  return acc;
+  return bell_row_any<T, XT, BS>(A, x, slice, lane, a);
 }
 
 // Block operator apply with x of type XT (x1 = x, x2 = x + n1).  When xcopy
@@ -1122,13 +1146,17 @@ __global__ void k_arnoldi_update(double* __restrict__ H, int ldh, double* __rest
   col[j + 1] = 0.0;
   g[j + 1] = -s * g[j];
   g[j] = c * g[j];
+  double cn2 = 0.0;
+  for (int i = 0; i <= j; ++i) cn2 += col[i] * col[i];
   out[0] = fabs(g[j + 1]);
   out[1] = hn;
   out[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+  out[3] = sqrt(cn2);
   if (out_host) {
     out_host[0] = out[0];
     out_host[1] = out[1];
     out_host[2] = out[2];
+    out_host[3] = out[3];
   }
 }
 

@@ -153,6 +153,7 @@ struct HostBell {
   int32_t n_nodes = 0, bs = 0, n_slices = 0;
   int64_t n_blocks = 0;
   std::vector<int32_t> slice_ptr, bcol;
+  std::vector<int16_t> bdel;  // bcol as deltas from the lane's node, when all fit in 16 bits
   std::vector<double> val;
   std::vector<int64_t> pos;  // CSR entry -> index into val
 };
@@ -218,12 +219,36 @@ static HostBell make_bell(const HostCSR& A, int bs) {
       off += cnt[(size_t)lane];
     }
   });
+  // 16-bit deltas from each lane's node when the band allows (lanes past the
+  // last node keep delta 0 and column 0)
+  bool fits = true;
+  for (int32_t sl = 0; sl < B.n_slices && fits; ++sl)
+    for (int64_t p = B.slice_ptr[sl]; p < B.slice_ptr[sl + 1] && fits; ++p)
+      for (int32_t lane = 0; lane < 64; ++lane) {
+        const int64_t node = (int64_t)sl * 64 + lane;
+        if (node >= B.n_nodes) break;
+        const int64_t d = (int64_t)B.bcol[(size_t)(p * 64 + lane)] - node;
+        if (d < -32767 || d > 32767) {
+          fits = false;
+          break;
+        }
+      }
+  if (fits) {
+    B.bdel.assign(B.bcol.size(), 0);
+    for (int32_t sl = 0; sl < B.n_slices; ++sl)
+      for (int64_t p = B.slice_ptr[sl]; p < B.slice_ptr[sl + 1]; ++p)
+        for (int32_t lane = 0; lane < 64; ++lane) {
+          const int64_t node = (int64_t)sl * 64 + lane;
+          if (node < B.n_nodes) B.bdel[(size_t)(p * 64 + lane)] = (int16_t)(B.bcol[(size_t)(p * 64 + lane)] - node);
+        }
+  }
   return B;
 }
 
 struct DevBell {
   int32_t n_nodes = 0, bs = 0, n_slices = 0;
   DBuf<int32_t> slice_ptr, bcol;
+  DBuf<int16_t> bdel;  // replaces bcol when the column deltas fit in 16 bits
   DBuf<double> v64;
   DBuf<float> v32;
   template <typename T>
@@ -234,8 +259,16 @@ struct DevBell {
     d.n_slices = n_slices;
     d.slice_ptr = slice_ptr.p;
     d.bcol = bcol.p;
-    if constexpr (sizeof(T) == 8) d.val = reinterpret_cast<const T*>(v64.p);
-    else d.val = reinterpret_cast<const T*>(v32.p);
+    d.bdel = bdel.p;
+    if constexpr (sizeof(T) == 8) {
+      d.val = reinterpret_cast<const T*>(v64.p);
+      d.stream = 1;
+    } else {
+      d.val = reinterpret_cast<const T*>(v32.p);
+      // more than three quarters of the 256 MB last-level cache: the values
+      // cannot stay there between passes, so they stream
+      d.stream = v32.n * sizeof(float) > (size_t(192) << 20) ? 1 : 0;
+    }
     return d;
   }
 };
@@ -245,7 +278,8 @@ static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipSt
   D.bs = H.bs;
   D.n_slices = H.n_slices;
   D.slice_ptr.upload(H.slice_ptr, s);
-  D.bcol.upload(H.bcol, s);
+  if (!H.bdel.empty()) D.bdel.upload(H.bdel, s);
+  else D.bcol.upload(H.bcol, s);
   if (f64) D.v64.upload(H.val, s);
   if (f32) {
     std::vector<float> v32(H.val.size());
@@ -1235,7 +1269,9 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
       const double* o = h.hbuf + 4 + 4 * sl;
       est = o[0] / r0;
       if (!std::isfinite(est)) api_fail(CAMG_ERR_NONFINITE, "non-finite residual estimate");
-      if (o[1] == 0.0) return true;  // happy breakdown
+      // happy breakdown: the new Arnoldi vector vanishes relative to the
+      // Hessenberg column, h_{j+1,j} <= 1e-300 ||H(:, j)||
+      if (o[1] <= 1e-300 * o[3]) return true;
       return !fixed && est <= o_rtol;
     };
     for (;;) {
@@ -1600,9 +1636,11 @@ int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out) {
     out->k_blocks = 0;
     out->k_slots = 0;
     out->transfer_layout = -1;
+    out->k_index_bytes = 0;
     if (!h->lev.empty()) {
       const DevLevel& D = h->lev[level];
       out->k_layout = D.bell ? 1 : (D.K.bs > 0 ? 2 : 0);
+      out->k_index_bytes = D.bell ? (D.Kb.bdel.p ? 2 : 4) : (D.K.bs > 0 ? 4 : 0);
       out->k_blocks = D.bell ? D.k_blocks : (D.K.bs > 0 ? (int64_t)D.K.bcol.n : 0);
       out->k_slots = D.k_slots;
       if (level + 1 < (int)h->lev.size()) out->transfer_layout = D.agg_ok ? 1 : 0;

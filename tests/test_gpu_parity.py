@@ -1010,3 +1010,49 @@ def test_dense_inverse_weak_scaling_coarsest():
     # the hierarchy built on that inverse solves the problem
     x, info = s.solve(torch.from_numpy(prob.b).cuda(), rtol=1e-8, max_iters=500)
     assert info["converged"], info
+
+
+def _permute_nodes(prob, seed):
+    """The same contact problem with its displacement nodes renumbered by a
+    seeded random permutation (multipliers unchanged)."""
+    import dataclasses
+
+    d = prob.dim
+    nn = prob.n_u // d
+    newnode_old = np.random.default_rng(seed).permutation(nn)  # new node -> old node
+    P = (newnode_old[:, None] * d + np.arange(d)[None, :]).ravel()  # new dof -> old dof
+    inv = np.empty_like(P)
+    inv[P] = np.arange(P.size)  # old dof -> new dof
+    K = prob.K.tocsr()[P][:, P].tocsr()
+    K.sort_indices()
+    G = prob.G.tocsr()[P].tocsr()
+    B = prob.B.tocsc()[:, P].tocsr()
+    B.sort_indices()
+    b = np.concatenate([prob.b[:prob.n_u][P], prob.b[prob.n_u:]])
+    return dataclasses.replace(
+        prob, K=K, G=G, B=B, b=b, slave_dofs=np.sort(inv[prob.slave_dofs]).astype(np.int32),
+        master_dofs=np.sort(inv[prob.master_dofs]).astype(np.int32), nullspace=prob.nullspace[P],
+        coords=prob.coords[newnode_old] if prob.coords.shape[0] == nn else prob.coords,
+        dirichlet=prob.dirichlet[np.concatenate([P, np.arange(prob.n_u, prob.n)])]
+        if prob.dirichlet.size == prob.n else prob.dirichlet[P],
+        top_dofs=np.sort(inv[prob.top_dofs]))
+
+
+def test_blocked_ell_block_index_widths():
+    """The fine level's blocked-ELL K keeps 16-bit block-column deltas when
+    the node numbering is banded (the generator's lexicographic order) and
+    full 32-bit indices when it is not (the same 40^3 problem with its nodes
+    shuffled); both V-cycles match the oracle's on their own problem."""
+    prob = make_workload("contact3d_40")
+    shuffled = _permute_nodes(prob, 12)
+    kw = dict(max_levels=2)
+    r = np.random.default_rng(6).standard_normal(prob.n)
+    for p, width in ((prob, 2), (shuffled, 4)):
+        s = _solver(p, **kw)
+        info = s.level_info(0)
+        assert info["k_layout"] == 1 and info["k_index_bytes"] == width, info
+        lv = build_hierarchy(p, OracleOptions(**kw))
+        for tr in (False, True):
+            z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+            ref = oracle_vcycle(lv, r, OracleOptions(**kw), transpose=tr)
+            assert _rel(z, ref) < 1e-12, (width, tr)
