@@ -505,6 +505,9 @@ namespace camg {
 
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Validates a caller's CSR block: the row pointers first, then the entries
+// of the rows in parallel chunks, reporting the error of the first
+// offending row (whichever chunk finds its own first).
 static void check_csr(const amg_csr& A, int64_t nrows, int64_t ncols, const char* name) {
   const std::string nm(name);
   if (A.nrows != nrows || A.ncols != ncols) api_fail(CAMG_ERR_SHAPE, nm + ": wrong dimensions");
@@ -513,14 +516,38 @@ static void check_csr(const amg_csr& A, int64_t nrows, int64_t ncols, const char
   if (A.nnz > 0 && (!A.col || !A.val)) api_fail(CAMG_ERR_INVALID_ARG, nm + ": col/val is NULL");
   if (nrows == 0) return;
   if (A.rowptr[0] != 0 || A.rowptr[nrows] != A.nnz) api_fail(CAMG_ERR_SHAPE, nm + ": rowptr ends do not match nnz");
-  for (int64_t i = 0; i < nrows; ++i) {
-    if (A.rowptr[i + 1] < A.rowptr[i]) api_fail(CAMG_ERR_SHAPE, nm + ": rowptr not monotone");
-    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
-      if (A.col[k] < 0 || A.col[k] >= ncols) api_fail(CAMG_ERR_SHAPE, nm + ": column index out of range");
-      if (k > A.rowptr[i] && A.col[k] <= A.col[k - 1]) api_fail(CAMG_ERR_SHAPE, nm + ": columns not sorted/unique");
-      if (!std::isfinite(A.val[k])) api_fail(CAMG_ERR_NONFINITE, nm + ": non-finite value");
-    }
-  }
+  // row pointers first (serially cheap), so the entry scan below stays in range
+  for (int64_t i = 0; i < nrows; ++i)
+    if (A.rowptr[i + 1] < A.rowptr[i] || A.rowptr[i + 1] > A.nnz)
+      api_fail(CAMG_ERR_SHAPE, nm + ": rowptr not monotone");
+  constexpr int64_t kGrain = 1 << 14;
+  const int64_t n_chunks = (nrows + kGrain - 1) / kGrain;
+  struct Bad {
+    int64_t row = -1;
+    int code = 0;
+    const char* what = nullptr;
+  };
+  std::vector<Bad> bad((size_t)n_chunks);
+  parallel_chunks(n_chunks, setup_threads(), [&](int64_t c, int) {
+    const int64_t r1 = std::min(nrows, (c + 1) * kGrain);
+    for (int64_t i = c * kGrain; i < r1; ++i)
+      for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+        if (A.col[k] < 0 || A.col[k] >= ncols) {
+          bad[(size_t)c] = {i, CAMG_ERR_SHAPE, ": column index out of range"};
+          return;
+        }
+        if (k > A.rowptr[i] && A.col[k] <= A.col[k - 1]) {
+          bad[(size_t)c] = {i, CAMG_ERR_SHAPE, ": columns not sorted/unique"};
+          return;
+        }
+        if (!std::isfinite(A.val[k])) {
+          bad[(size_t)c] = {i, CAMG_ERR_NONFINITE, ": non-finite value"};
+          return;
+        }
+      }
+  });
+  for (const Bad& b : bad)
+    if (b.row >= 0) api_fail(b.code, nm + b.what);
 }
 
 static HostCSR to_host(const amg_csr& A) {
@@ -529,8 +556,12 @@ static HostCSR to_host(const amg_csr& A) {
   H.ncols = A.ncols;
   H.rp.assign(A.rowptr, A.rowptr + A.nrows + 1);
   if (A.nnz) {
-    H.ci.assign(A.col, A.col + A.nnz);
-    H.v.assign(A.val, A.val + A.nnz);
+    H.ci.resize((size_t)A.nnz);
+    H.v.resize((size_t)A.nnz);
+    parallel_for(A.nnz, [&](int64_t k0, int64_t k1) {
+      std::memcpy(H.ci.data() + k0, A.col + k0, (size_t)(k1 - k0) * sizeof(int32_t));
+      std::memcpy(H.v.data() + k0, A.val + k0, (size_t)(k1 - k0) * sizeof(double));
+    }, int64_t(1) << 22);
   }
   return H;
 }
