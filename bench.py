@@ -75,7 +75,7 @@ def smooth_u_bytes(info0, nnz_K_true, elem):
     return b, b
 
 
-def vcycle_matrix_bytes(solver, elem):
+def vcycle_matrix_bytes(solver, elem, fine_k_value_bytes=None):
     """Matrix bytes streamed by one forward V-cycle (a lower bound on its
     traffic: vectors excluded).  Per smoothing level with nu_pre + nu_post
     sweeps of nj Jacobi steps: K is read (nu_pre + nu_post) * nj times (each
@@ -85,7 +85,8 @@ def vcycle_matrix_bytes(solver, elem):
     (bs x bs blocks with a 2- or 4-byte block index, or CSR), P and R either CSR or
     index-free (values plus one 4-byte base column per fine row for P, one
     4-byte row index per fine row for R), the other blocks CSR (value +
-    4-byte column).  The coarsest level: its dense inverse."""
+    4-byte column).  The coarsest level: its dense inverse.  fine_k_value_bytes
+    overrides the value size of a blocked-ELL level-0 K (bfloat16 storage)."""
     o = solver.options
     sweeps = o.nu_pre + o.nu_post
     nj = max(1, o.jacobi_sweeps)
@@ -97,7 +98,8 @@ def vcycle_matrix_bytes(solver, elem):
             total += n * n * elem
             break
         if info["k_layout"] in (1, 2):
-            kb = info["k_blocks"] * (info["k_bs"] ** 2 * elem + info["k_index_bytes"])
+            ve = fine_k_value_bytes if (l == 0 and fine_k_value_bytes and info["k_layout"] == 1) else elem
+            kb = info["k_blocks"] * (info["k_bs"] ** 2 * ve + info["k_index_bytes"])
         else:
             kb = info["nnz_K"] * (elem + 4)
         e = elem + 4
@@ -188,7 +190,7 @@ def main():
     b = torch.from_numpy(prob.b).cuda()
 
     solvers, setup_s = {}, {}
-    for name, prec in (("mixed", 1), ("fp64", 0)):
+    for name, prec in (("mixed", 1), ("fp64", 0), ("mixed_bf16", 2)):
         t1 = time.time()
         solvers[name] = AMGSolver.from_problem(
             prob, AMGOptions(max_levels=args.levels, precision=prec, spmv_format=args.spmv_format))
@@ -205,9 +207,9 @@ def main():
         return fi, ai, dA
 
     results, xs = {}, {}
-    for name in ("fp64", "mixed"):
+    for name in ("fp64", "mixed_bf16", "mixed"):
         s = solvers[name]
-        # the FP64 path is the comparison: fewer timed steps
+        # the FP64 and bfloat16-storage paths are comparisons: fewer timed steps
         n_steps = args.steps if name == "mixed" else max(1, min(args.steps, args.fp64_steps))
         n_warm = args.warmup if name == "mixed" else min(args.warmup, 1)
         for _ in range(n_warm):
@@ -260,8 +262,10 @@ def main():
     achieved = bytes_alg / avg_s / 1e9
     peak = 8000.0
     traffic = measured_traffic(args.workload) if info0["k_layout"] == 1 else None
-    vc_bytes = {"mixed": vcycle_matrix_bytes(solvers["mixed"], 4), "fp64": vcycle_matrix_bytes(solvers["fp64"], 8)}
+    vc_bytes = {"mixed": vcycle_matrix_bytes(solvers["mixed"], 4), "fp64": vcycle_matrix_bytes(solvers["fp64"], 8),
+                "mixed_bf16": vcycle_matrix_bytes(solvers["mixed_bf16"], 4, fine_k_value_bytes=2)}
     diff = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+    diff16 = float(np.linalg.norm(xs["mixed_bf16"] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
 
     def summary(name):
         r = results[name]
@@ -304,6 +308,9 @@ def main():
         },
         "mixed": summary("mixed"),
         "fp64": summary("fp64"),
+        "mixed_bf16": dict(summary("mixed_bf16"), solution_rel_diff_vs_fp64=diff16,
+                           note="option CAMG_PREC_MIXED_BF16: as mixed, with the fine level's K stored in bfloat16 "
+                                "for the V-cycle (FP32 arithmetic); not the headline, which keeps the FP32 hierarchy"),
         "vcycle_bytes_model": "matrix streams of one forward V-cycle (K in its device layout, G, B, C, R, P, the "
                               "dense coarsest inverse), vectors excluded: a lower bound on its traffic",
         "speedup_mixed_vs_fp64": solve_fp64 / solve_mixed,

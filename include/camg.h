@@ -100,6 +100,10 @@ typedef struct {
 #define CAMG_JACOBI_DIAG 1       /* Jacobi prediction relaxes with diag(K)  */
 #define CAMG_PREC_FP64 0         /* hierarchy, smoother, transfers in FP64  */
 #define CAMG_PREC_MIXED 1        /* ... in FP32 inside the FP64 FGMRES      */
+#define CAMG_PREC_MIXED_BF16 2   /* as MIXED, with the fine level's K stored in bfloat16 for the V-cycle
+                                    when it has the sliced blocked-ELL layout (FP32 arithmetic: each
+                                    value FP64 -> FP32 -> bfloat16, nearest even, widened on load); the
+                                    outer operator keeps K in FP64 */
 #define CAMG_SPMV_AUTO 0         /* K as sliced blocked-ELL on large levels */
 #define CAMG_SPMV_CSR 1          /* K as CSR on every level                 */
 #define CAMG_SPMV_BELL 2         /* K as sliced blocked-ELL on every level  */

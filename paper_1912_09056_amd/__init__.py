@@ -5,7 +5,7 @@ for saddle point systems from mortar contact formulations).
 The solver lives in the HIP library libcamg.so (C-ABI in include/camg.h);
 this package is its Python binding plus a differentiable wrapper.
 """
-from .camg import AMGOptions, AMGSolver, CamgError, PREC_FP64, PREC_MIXED, load_library
+from .camg import AMGOptions, AMGSolver, CamgError, PREC_FP64, PREC_MIXED, PREC_MIXED_BF16, load_library
 from .autograd import ContactSolve, contact_solve
 
 __all__ = [
@@ -14,6 +14,7 @@ __all__ = [
     "CamgError",
     "PREC_FP64",
     "PREC_MIXED",
+    "PREC_MIXED_BF16",
     "load_library",
     "ContactSolve",
     "contact_solve",

@@ -23,6 +23,7 @@ CAMG_OK = 0
 CAMG_NOT_CONVERGED = 1
 PREC_FP64 = 0
 PREC_MIXED = 1
+PREC_MIXED_BF16 = 2
 KCLASS_SMOOTH_U = 1
 KCLASS_OPERATOR = 2
 KCLASS_ORTHO = 4

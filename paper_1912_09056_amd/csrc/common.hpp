@@ -112,6 +112,9 @@ struct DBELL {
   const int32_t* bcol = nullptr;
   const int16_t* bdel = nullptr;
   const T* val = nullptr;
+  // FP32 views only: the values as bfloat16 words (the upper halves of the
+  // FP32 words, rounded to nearest even) in place of val, same layout
+  const uint16_t* val16 = nullptr;
 };
 
 }  // namespace camg

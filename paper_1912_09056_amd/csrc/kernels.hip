@@ -696,6 +696,15 @@ __device__ __forceinline__ T bell_val(const T* p) {
   else return *p;
 }
 
+// A bfloat16 value widened to FP32 (exact: the word's upper half).
+template <bool NT>
+__device__ __forceinline__ float bell_val16(const uint16_t* p) {
+  uint32_t u;
+  if constexpr (NT) u = __builtin_nontemporal_load(p);
+  else u = *p;
+  return __uint_as_float(u << 16);
+}
+
 // Block column of position p for lane `lane` of slice `slice`: a 16-bit
 // delta from the lane's node (DEL) or the full index.
 // base: the lane's node, or 0 for the lanes past the last node (their
@@ -709,38 +718,57 @@ __device__ __forceinline__ int bell_col(const DBELL<T>& A, int64_t p, int base, 
 // Row (node 64*slice + lane, component a) of a BELL matrix times x (x
 // converted to T on load).  BS > 0 is the compile-time block size; BS == 0
 // reads it at run time.  DEL: 16-bit column deltas; NT: nontemporal value
-// loads (both chosen per matrix outside the loop, so each loop has one kind
-// of load).
-template <typename T, typename XT, int BS, bool DEL, bool NT>
+// loads; B16: bfloat16 values widened to FP32 (all three chosen per matrix
+// outside the loop, so each loop has one kind of load).
+template <typename T, typename XT, int BS, bool DEL, bool NT, bool B16>
 __device__ __forceinline__ T bell_row_impl(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
   const int bs = BS > 0 ? BS : A.bs;
   const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
   const int node = slice * 64 + lane;
   const int base = node < A.n_nodes ? node : 0;
   T acc = T(0);
-#pragma unroll 4
+#pragma unroll 2
   for (int p = p0; p < p1; ++p) {
     const int c = bell_col<T, DEL>(A, p, base, lane);
-    const T* __restrict__ v = A.val + ((int64_t)p * (bs * bs) + a * bs) * 64 + lane;
+    const int64_t off = ((int64_t)p * (bs * bs) + a * bs) * 64 + lane;
     const XT* __restrict__ xc = x + (int64_t)c * bs;
-    if (BS > 0) {
+    if constexpr (B16) {
+      const uint16_t* __restrict__ v = A.val16 + off;
+      if (BS > 0) {
 #pragma unroll
-      for (int b = 0; b < BS; ++b) acc += bell_val<T, NT>(v + b * 64) * (T)xc[b];
+        for (int b = 0; b < BS; ++b) acc += (T)bell_val16<NT>(v + b * 64) * (T)xc[b];
+      } else {
+        for (int b = 0; b < bs; ++b) acc += (T)bell_val16<NT>(v + b * 64) * (T)xc[b];
+      }
     } else {
-      for (int b = 0; b < bs; ++b) acc += bell_val<T, NT>(v + b * 64) * (T)xc[b];
+      const T* __restrict__ v = A.val + off;
+      if (BS > 0) {
+#pragma unroll
+        for (int b = 0; b < BS; ++b) acc += bell_val<T, NT>(v + b * 64) * (T)xc[b];
+      } else {
+        for (int b = 0; b < bs; ++b) acc += bell_val<T, NT>(v + b * 64) * (T)xc[b];
+      }
     }
   }
   return acc;
 }
 
+template <typename T, typename XT, int BS, bool B16>
+__device__ __forceinline__ T bell_row_vals(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
+  if (A.bdel) {
+    if (A.stream) return bell_row_impl<T, XT, BS, true, true, B16>(A, x, slice, lane, a);
+    return bell_row_impl<T, XT, BS, true, false, B16>(A, x, slice, lane, a);
+  }
+  if (A.stream) return bell_row_impl<T, XT, BS, false, true, B16>(A, x, slice, lane, a);
+  return bell_row_impl<T, XT, BS, false, false, B16>(A, x, slice, lane, a);
+}
+
 template <typename T, typename XT, int BS>
 __device__ __forceinline__ T bell_row_any(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
-  if (A.bdel) {
-    if (A.stream) return bell_row_impl<T, XT, BS, true, true>(A, x, slice, lane, a);
-    return bell_row_impl<T, XT, BS, true, false>(A, x, slice, lane, a);
+  if constexpr (sizeof(T) == 4) {
+    if (A.val16) return bell_row_vals<T, XT, BS, true>(A, x, slice, lane, a);
   }
-  if (A.stream) return bell_row_impl<T, XT, BS, false, true>(A, x, slice, lane, a);
-  return bell_row_impl<T, XT, BS, false, false>(A, x, slice, lane, a);
+  return bell_row_vals<T, XT, BS, false>(A, x, slice, lane, a);
 }
 
 template <typename T, int BS>

@@ -251,6 +251,7 @@ struct DevBell {
   DBuf<int16_t> bdel;  // replaces bcol when the column deltas fit in 16 bits
   DBuf<double> v64;
   DBuf<float> v32;
+  DBuf<uint16_t> v16;  // bfloat16 words in place of v32 (fine-level K with CAMG_PREC_MIXED_BF16)
   template <typename T>
   DBELL<T> view() const {
     DBELL<T> d;
@@ -265,15 +266,19 @@ struct DevBell {
       d.stream = 1;
     } else {
       d.val = reinterpret_cast<const T*>(v32.p);
+      d.val16 = v16.p;
       // more than three quarters of the 256 MB last-level cache: the values
       // cannot stay there between passes, so they stream
-      d.stream = v32.n * sizeof(float) > (size_t(192) << 20) ? 1 : 0;
+      const size_t bytes = v16.p ? v16.n * sizeof(uint16_t) : v32.n * sizeof(float);
+      d.stream = bytes > (size_t(192) << 20) ? 1 : 0;
     }
     return d;
   }
 };
 
-static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipStream_t s) {
+// b16: the reduced copy holds bfloat16 words (FP64 -> FP32 -> bfloat16,
+// each to nearest even) instead of FP32 values.
+static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipStream_t s, bool b16 = false) {
   D.n_nodes = H.n_nodes;
   D.bs = H.bs;
   D.n_slices = H.n_slices;
@@ -281,7 +286,21 @@ static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipSt
   if (!H.bdel.empty()) D.bdel.upload(H.bdel, s);
   else D.bcol.upload(H.bcol, s);
   if (f64) D.v64.upload(H.val, s);
-  if (f32) {
+  if (f32 && b16) {
+    std::vector<uint16_t> v16(H.val.size());
+    parallel_for((int64_t)v16.size(), [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        const float f = (float)H.val[(size_t)i];
+        uint32_t u;
+        std::memcpy(&u, &f, sizeof(u));
+        const uint32_t lower = u & 0xFFFFu, upper = u >> 16;
+        const uint32_t up = (lower > 0x8000u || (lower == 0x8000u && (upper & 1u))) ? 1u : 0u;
+        v16[(size_t)i] = (uint16_t)(upper + up);
+      }
+    });
+    D.v16.upload(v16, s);
+    CAMG_HIP(hipStreamSynchronize(s));
+  } else if (f32) {
     std::vector<float> v32(H.val.size());
     parallel_for((int64_t)v32.size(), [&](int64_t i0, int64_t i1) {
       for (int64_t i = i0; i < i1; ++i) v32[(size_t)i] = (float)H.val[(size_t)i];
@@ -613,7 +632,7 @@ static void alloc_vecs(LevelVecs<T>& V, const HostLevel& H, bool dense_coarse, h
 }
 
 static void upload_hierarchy(amg_handle& h, hipStream_t s) {
-  const bool mixed = h.opts.precision == CAMG_PREC_MIXED;
+  const bool mixed = h.opts.precision != CAMG_PREC_FP64;
   const size_t L = h.host.size();
   h.lev.resize(L);
   for (size_t l = 0; l < L; ++l) {
@@ -654,8 +673,9 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
           h.d_bpos_KT.upload(posT, s);
           CAMG_HIP(hipStreamSynchronize(s));
         }
-        upload_bell(D.Kb, hb, f64, f32, s);
-        upload_bell(D.KTb, hbt, f64, f32, s);
+        const bool b16 = l == 0 && h.opts.precision == CAMG_PREC_MIXED_BF16;
+        upload_bell(D.Kb, hb, f64, f32, s, b16);
+        upload_bell(D.KTb, hbt, f64, f32, s, b16);
         D.k_blocks = hb.n_blocks;
         D.k_slots = (int64_t)hb.slice_ptr.back() * 64;
       } else {
@@ -1081,7 +1101,7 @@ static T* vcycle_run(amg_handle& h, bool transpose, hipStream_t s) {
 
 static void vcycle_to(amg_handle& h, bool transpose, double* z, hipStream_t s) {
   const int64_t n = h.lev[0].n();
-  if (h.opts.precision == CAMG_PREC_MIXED) {
+  if (h.opts.precision != CAMG_PREC_FP64) {
     float* out = vcycle_run<float>(h, transpose, s);
     cast_f2d(out, z, n, s);
   } else {
@@ -1094,7 +1114,7 @@ static void vcycle_to(amg_handle& h, bool transpose, double* z, hipStream_t s) {
 static void precondition(amg_handle& h, bool transpose, const double* r, double* z, hipStream_t s) {
   DevLevel& D0 = h.lev[0];
   const int64_t n = D0.n();
-  if (h.opts.precision == CAMG_PREC_MIXED) cast_d2f(r, D0.v32.b.p, n, s);
+  if (h.opts.precision != CAMG_PREC_FP64) cast_d2f(r, D0.v32.b.p, n, s);
   else copy_vec<double>(r, D0.v64.b.p, n, s);
   vcycle_to(h, transpose, z, s);
 }
@@ -1238,7 +1258,7 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
     status = CAMG_OK;
   } else {
     const bool fused = (m + 1 <= 64);
-    const bool mixed = h.opts.precision == CAMG_PREC_MIXED;
+    const bool mixed = h.opts.precision != CAMG_PREC_FP64;
     DevLevel& D0 = h.lev[0];
     // Launches Arnoldi step j: v_j, z_j = M^-1 v_j, w = A z_j, CGS2, Givens;
     // leaves w / ||w|| scaling for the next step's prep and copies the
@@ -1457,7 +1477,7 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   if (opts) o = *opts;
   if (p->dim < 1 || p->dim > 3) api_fail(CAMG_ERR_INVALID_ARG, "dim must be 1..3");
   if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
-      (o.precision != CAMG_PREC_FP64 && o.precision != CAMG_PREC_MIXED) || o.atilde < 0 || o.atilde > 2 ||
+      o.precision < CAMG_PREC_FP64 || o.precision > CAMG_PREC_MIXED_BF16 || o.atilde < 0 || o.atilde > 2 ||
       (o.atilde == CAMG_ATILDE_NODAL && o.jacobi_diag != CAMG_JACOBI_ATILDE) ||
       o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
       o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 2 || o.schur_sweeps < 1 ||
@@ -1787,7 +1807,7 @@ int amg_vcycle_apply_noalloc(amg_handle* h, int transpose, const double* r, doub
     need_device(h);
     if (!h->scratch) api_fail(CAMG_ERR_INVALID_ARG, "handle has no scratch address");
     CAMG_HIP(hipSetDevice(h->device));
-    if (h->opts.precision == CAMG_PREC_MIXED) vcycle_noalloc<float>(*h, transpose != 0, r, z, as_stream(stream));
+    if (h->opts.precision != CAMG_PREC_FP64) vcycle_noalloc<float>(*h, transpose != 0, r, z, as_stream(stream));
     else vcycle_noalloc<double>(*h, transpose != 0, r, z, as_stream(stream));
     return CAMG_OK;
   });

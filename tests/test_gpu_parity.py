@@ -1056,3 +1056,40 @@ def test_blocked_ell_block_index_widths():
             z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
             ref = oracle_vcycle(lv, r, OracleOptions(**kw), transpose=tr)
             assert _rel(z, ref) < 1e-12, (width, tr)
+
+
+@pytest.mark.parametrize("name,levels", [("contact3d_6", 2), ("contact3d_40", 4)])
+def test_bf16_fine_level_storage(name, levels):
+    """precision = mixed with bfloat16 storage of the fine level's K (sliced
+    blocked-ELL): the V-cycle and its transpose against the oracle's V-cycle
+    on the hierarchy whose level-0 K holds the bfloat16-rounded values (FP32
+    arithmetic: 2e-5), and the solve reaching 1e-8 with the FP64 true
+    residual, within a few iterations of the FP32 hierarchy's count and with
+    a solution within 1e-7 of the FP64 solve."""
+    from oracle.storage import fine_k_bf16_levels
+    from paper_1912_09056_amd.camg import PREC_MIXED_BF16
+
+    prob = make_workload(name)
+    kw = dict(max_levels=levels)
+    lv = fine_k_bf16_levels(build_hierarchy(prob, OracleOptions(**kw)))
+    s16 = _solver(prob, precision=PREC_MIXED_BF16, fmt=2, **kw)
+    rng = np.random.default_rng(9)
+    for tr in (False, True):
+        r = rng.standard_normal(prob.n)
+        z = s16.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
+        ref = oracle_vcycle(lv, r, OracleOptions(**kw), transpose=tr)
+        assert _rel(z, ref) < 2e-5, tr
+    b = torch.from_numpy(prob.b)
+    x16, i16 = s16.solve(b, rtol=1e-8)
+    s32 = _solver(prob, precision=1, fmt=2, **kw)
+    x32, i32 = s32.solve(b, rtol=1e-8)
+    x64, _ = _solver(prob, precision=0, fmt=2, **kw).solve(b, rtol=1e-12)
+    A = prob.full_matrix()
+    xh = x16.cpu().numpy()
+    res = np.linalg.norm(prob.b - A @ xh) / np.linalg.norm(prob.b)
+    err = _rel(xh, x64.cpu().numpy())
+    print(f"[bf16] {name}: iterations bf16 {i16['iters']} fp32 {i32['iters']}, residual {res:.2e}, "
+          f"error vs FP64 {err:.2e}", flush=True)
+    assert i16["converged"] and res <= 1.0001e-8
+    assert i16["iters"] <= i32["iters"] + 3
+    assert err < 1e-7
