@@ -48,10 +48,16 @@ def copy_probe(mib):
     n = mib * (1 << 20) // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
     for _ in range(5):
         y.copy_(x)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}), flush=True)
+    b.record()
+    b.synchronize()
+    s = a.elapsed_time(b) * 1e-3 / 5
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 6, "us_per_copy": s * 1e6,
+                      "read_plus_write_GBps": 2 * n * 4 / s / 1e9}), flush=True)
 
 
 def smooth_u_bytes(info0, nnz_K_true, elem):
