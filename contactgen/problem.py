@@ -133,6 +133,24 @@ def _assemble_body(nelem, axes, lam_e, mu_e, Klam, Kmu):
     return sp.csr_matrix((data, indices, indptr), shape=(n_nodes * dim, n_nodes * dim))
 
 
+def exact_symmetric(K: sp.csr_matrix) -> sp.csr_matrix:
+    """(K + K^T) / 2, which equals its transpose bit for bit.
+
+    The stiffness matrix is symmetric, but the floating-point sums of the
+    element contributions reach K_ij and K_ji in different orders: mirrored
+    entries differ by a few units in the last place, and a coupling that
+    cancels may come out as an exact zero on one side only.  K_ij + K_ji is
+    the same sum for both entries and the halving is exact, so the mean is
+    symmetric in value and pattern (entries that are exact zeros dropped,
+    indices sorted)."""
+    K = sp.csr_matrix(K)
+    S = (K + K.T.tocsr()).tocsr()
+    S.data *= 0.5
+    S.eliminate_zeros()
+    S.sort_indices()
+    return S
+
+
 def _element_shapes(nelem, axes, shift):
     """Element matrices (Klam, Kmu) for every distinct element shape.
 
@@ -392,6 +410,7 @@ def make_contact_problem(
         Mx.sum_duplicates()
         mats.append(Mx)
     K, G, Bm, Cm = mats
+    K = exact_symmetric(K)
 
     # right-hand side
     top_dofs = slave_top_nodes * dim + last
@@ -558,7 +577,7 @@ def rotate_problem(p: ContactProblem, angle_y: float, angle_z: float) -> Contact
     b[: p.n_u] = Q @ p.b[: p.n_u]
     return ContactProblem(
         dim=d,
-        K=clean(K),
+        K=exact_symmetric(clean(K)),
         G=clean(Q @ p.G @ Ql.T),
         B=clean(p.B @ Q.T),
         C=clean(p.C @ Ql.T),

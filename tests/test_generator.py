@@ -297,3 +297,37 @@ def test_rotated_problem_has_the_rotated_solution():
     assert np.sort(KZ[free])[free.sum() // 2] <= 1e-12 * np.abs(q.K.data).max()
     with pytest.raises(ValueError):
         rotate_problem(make_contact_problem(3, (2, 2, 2), (3, 3, 2)), 0.1, 0.2)  # roller: partial clamps
+
+
+def test_exact_symmetric_mean_of_mirrors():
+    """(K + K^T)/2 entry by entry: mirrored entries become the same number,
+    an entry stored on one side only appears on both with half its value,
+    and exact zeros are dropped."""
+    from contactgen.problem import exact_symmetric
+
+    K = sp.csr_matrix(np.array([[4.0, 1.0 + 2.0 ** -52, 0.0],
+                                [1.0, 3.0, 2.0 ** -60],
+                                [0.0, 0.0, 0.0]]))
+    S = exact_symmetric(K).toarray()
+    assert np.array_equal(S, S.T)
+    assert S[0, 1] == (1.0 + 2.0 ** -52 + 1.0) / 2
+    assert S[1, 2] == S[2, 1] == 2.0 ** -61
+    assert exact_symmetric(K).nnz == 6
+
+
+@pytest.mark.parametrize("name", ["contact2d_16", "contact3d_6", "contact3d_150_curved"])
+def test_stiffness_equals_its_transpose_bit_for_bit(name):
+    """The generator's K equals K^T exactly (pattern and values), also on the
+    curved geometry and after a rotation of the whole problem."""
+    from contactgen.problem import rotate_problem
+
+    kw = dict(slave_elems=(4, 4, 4), master_elems=(5, 5, 4)) if name == "contact3d_150_curved" else {}
+    probs = [make_workload(name, **kw)]
+    if name == "contact3d_6":
+        probs.append(rotate_problem(make_contact_problem(3, (4, 4, 3), (5, 5, 3), top_bc="clamped"), 0.3, 0.2))
+    for p in probs:
+        K = p.K.tocsr()
+        Kt = K.T.tocsr()
+        Kt.sort_indices()
+        assert np.array_equal(K.indptr, Kt.indptr) and np.array_equal(K.indices, Kt.indices)
+        assert np.array_equal(K.data, Kt.data)
