@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="FGMRES iterations of the oracle in the CPU sample (0: sized to about 20 s)")
     ap.add_argument("--fp64-steps", type=int, default=5, help="timed steps of the FP64 comparison path")
-    ap.add_argument("--spmv-format", type=int, default=0, help="device storage of K: 0 auto, 1 CSR, 2 blocked-ELL")
+    ap.add_argument("--spmv-format", type=int, default=0,
+                    help="device storage of K: 0 auto, 1 CSR, 2 blocked-ELL; +4: no symmetric storage")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times) and exit; used to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -71,9 +72,19 @@ def smooth_u_bytes(info0, nnz_K_true, elem):
     per nonzero bs x bs block;
     `stored` counts every value of those blocks (including the zeros a block
     holds) and is what the kernel actually streams (slice padding is in
-    neither).  CSR layout: K's entries (value + column), both the same."""
+    neither).  Symmetric storage (k_layout 3): only the blocks on and right
+    of the block diagonal are stored and streamed (their true nonzeros, or
+    all their values), with a 2-byte delta each, plus a 2-byte delta and a
+    2-byte mirror position per block left of it (those blocks are the
+    stored ones read again, transposed).  CSR layout: K's entries (value +
+    column), both the same."""
     n_u, n_l = info0["n_u"], info0["n_l"]
     vec = n_u * elem * 4 + n_l * elem + info0["nnz_G"] * (elem + 4) + (n_u + 1) * 4
+    if info0["k_layout"] == 3:
+        bs = info0["k_bs"]
+        up = info0["k_blocks"] - info0["k_lower_blocks"]
+        idx = up * 2 + info0["k_lower_blocks"] * 4
+        return info0["k_nnz_stored"] * elem + idx + vec, up * bs * bs * elem + idx + vec
     if info0["k_layout"] == 1:
         bs, ib = info0["k_bs"], info0["k_index_bytes"]
         return nnz_K_true * elem + info0["k_blocks"] * ib + vec, info0["k_blocks"] * (bs * bs * elem + ib) + vec
@@ -88,7 +99,9 @@ def vcycle_matrix_bytes(solver, elem, fine_k_value_bytes=None):
     sweep but the first from zero, its extra Jacobi steps, and the residual
     before restriction); G twice per sweep plus the residual; B and C once
     per sweep plus the residual; R and P once.  K in its device layout
-    (bs x bs blocks with a 2- or 4-byte block index, or CSR), P and R either CSR or
+    (bs x bs blocks with a 2- or 4-byte block index; in symmetric storage the
+    blocks on and right of the diagonal plus 4 index bytes per block left of
+    it; or CSR), P and R either CSR or
     index-free (values plus one 4-byte base column per fine row for P, one
     4-byte row index per fine row for R), the other blocks CSR (value +
     4-byte column).  The coarsest level: its dense inverse.  fine_k_value_bytes
@@ -103,7 +116,11 @@ def vcycle_matrix_bytes(solver, elem, fine_k_value_bytes=None):
             n = info["n_u"] + info["n_l"]
             total += n * n * elem
             break
-        if info["k_layout"] in (1, 2):
+        if info["k_layout"] == 3:
+            ve = fine_k_value_bytes if (l == 0 and fine_k_value_bytes) else elem
+            low = info["k_lower_blocks"]
+            kb = (info["k_blocks"] - low) * (info["k_bs"] ** 2 * ve + 2) + low * 4
+        elif info["k_layout"] in (1, 2):
             ve = fine_k_value_bytes if (l == 0 and fine_k_value_bytes and info["k_layout"] == 1) else elem
             kb = info["k_blocks"] * (info["k_bs"] ** 2 * ve + info["k_index_bytes"])
         else:
@@ -267,7 +284,11 @@ def main():
     bytes_alg, bytes_stored = smooth_u_bytes(info0, prob.K.nnz, 4)
     achieved = bytes_alg / avg_s / 1e9
     peak = 8000.0
-    traffic = measured_traffic(args.workload) if info0["k_layout"] == 1 else None
+    traffic = measured_traffic(args.workload) if info0["k_layout"] in (1, 3) else None
+    sym = info0["k_layout"] == 3
+    # the same operator's bytes in the full blocked layout (every nonzero block
+    # stored, 2-byte deltas): what a full-storage pass would have to stream
+    full_bytes = smooth_u_bytes(dict(info0, k_layout=1, k_index_bytes=2), prob.K.nnz, 4)[0] if sym else bytes_alg
     vc_bytes = {"mixed": vcycle_matrix_bytes(solvers["mixed"], 4), "fp64": vcycle_matrix_bytes(solvers["fp64"], 8),
                 "mixed_bf16": vcycle_matrix_bytes(solvers["mixed_bf16"], 4, fine_k_value_bytes=2)}
     diff = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
@@ -323,7 +344,9 @@ def main():
         "mixed_vs_fp64_solution_rel_diff": diff,
         "paper_context": PAPER_CONTEXT,
         "roofline": {
-            "kernel": "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell: sliced blocked-ELL K)"
+            "kernel": ("level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell: sliced blocked-ELL K, "
+                       "symmetric storage)") if sym else
+                      "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell: sliced blocked-ELL K)"
                       if info0["k_layout"] == 1 else "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u: CSR K)",
             "bound": "hbm",
             "achieved": achieved,
@@ -333,7 +356,11 @@ def main():
             "traffic": traffic,
             "achieved_from_counters_GBps": traffic / avg_s / 1e9 if traffic else None,
             "bytes_per_launch": bytes_alg,
-            "bytes_model": f"K's true nonzeros (one FP32 value each) + one {info0['k_index_bytes']}-byte block-column "
+            "bytes_model": ("K's true nonzeros in the stored blocks (on and right of the block diagonal; one FP32 "
+                            "value each) + a 2-byte delta per stored block + a 2-byte delta and a 2-byte mirror "
+                            "position per block left of the diagonal + G CSR + row pointers + 5 FP32 vectors of "
+                            "n_u, read or written once") if sym else
+                           f"K's true nonzeros (one FP32 value each) + one {info0['k_index_bytes']}-byte block-column "
                            "index per nonzero 3x3 block + G CSR + row pointers + 5 FP32 vectors of n_u, read or "
                            "written once",
             "bytes_per_launch_stored": bytes_stored,
@@ -341,7 +368,13 @@ def main():
             "stored_bytes_model": "as bytes_model but every value of each nonzero 3x3 block (the zeros a block "
                                   "holds included): what the kernel streams",
             "nnz_K": prob.K.nnz,
+            "full_storage_bytes_per_launch": full_bytes,
+            "full_storage_equivalent_GBps": full_bytes / avg_s / 1e9,
+            "k_layout": {1: "sliced blocked-ELL", 3: "sliced blocked-ELL, symmetric storage"}.get(
+                info0["k_layout"], "CSR"),
             "k_blocks": info0["k_blocks"],
+            "k_lower_blocks": info0["k_lower_blocks"],
+            "k_nnz_stored": info0["k_nnz_stored"],
             "k_slots_with_padding": info0["k_slots"],
             "avg_launch_us": avg_s * 1e6,
             "launches": n_launch,

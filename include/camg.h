@@ -107,6 +107,8 @@ typedef struct {
 #define CAMG_SPMV_AUTO 0         /* K as sliced blocked-ELL on large levels */
 #define CAMG_SPMV_CSR 1          /* K as CSR on every level                 */
 #define CAMG_SPMV_BELL 2         /* K as sliced blocked-ELL on every level  */
+#define CAMG_SPMV_FULL 4         /* flag (AUTO or BELL | FULL): a blocked-ELL K that equals its transpose
+                                    exactly is kept in full, not in symmetric storage */
 #define CAMG_PROLONG_TENTATIVE 0 /* displacement transfers: tentative (PA)  */
 #define CAMG_PROLONG_SMOOTHED 1  /* ... smoothed aggregation (SA)           */
 #define CAMG_SCHUR_DIAG 0        /* Schur diagonal: diag(B Atilde^-1 G - C) */
@@ -125,7 +127,8 @@ typedef struct {
   int32_t atilde;          /* CAMG_ATILDE_* (NODAL needs jacobi_diag = CAMG_JACOBI_ATILDE) */
   int32_t jacobi_diag;     /* CAMG_JACOBI_*                                */
   int32_t precision;       /* CAMG_PREC_*                                  */
-  int32_t spmv_format;     /* CAMG_SPMV_* (storage of K on device)         */
+  int32_t spmv_format;     /* CAMG_SPMV_* (storage of K on device); blocked-ELL levels whose K equals
+                              its transpose bit for bit use symmetric storage unless CAMG_SPMV_FULL is set */
   int32_t graphs;          /* 1: capture the V-cycle once into a HIP graph and replay it */
   double jacobi_omega;     /* Jacobi damping                               */
   double simple_alpha;     /* block damping alpha (Alg. 3; see smoother), > 0 */
@@ -209,7 +212,10 @@ typedef struct {
   int64_t n_agg_u, n_agg_l; /* aggregates built on this level (0 on the coarsest) */
   double op_complexity;   /* sum over levels of nnz / level-0 nnz (all blocks) */
   int32_t k_layout;       /* device storage of K: 0 CSR, 1 sliced blocked-ELL, 2 CSR plus a node-blocked
-                             copy used by the row dots (-1: host-only handle) */
+                             copy used by the row dots, 3 sliced blocked-ELL in symmetric storage (K = K^T
+                             exactly: the blocks on and right of the block diagonal are stored, each block
+                             left of it is read transposed from its mirror; it serves K and K^T)
+                             (-1: host-only handle) */
   int32_t k_bs;           /* block size of the blocked layout                */
   int64_t k_blocks;       /* nonzero bs x bs blocks of K (blocked layouts)   */
   int64_t k_slots;        /* stored blocks including slice padding           */
@@ -219,6 +225,12 @@ typedef struct {
   int32_t k_index_bytes;  /* bytes per stored block-column index of the blocked layouts: 2 when the
                              columns are kept as 16-bit deltas from the row's node, else 4 (0: CSR
                              or host-only) */
+  int64_t k_lower_blocks; /* symmetric storage: nonzero blocks left of the block diagonal, read through
+                             their mirrors (each costs a 2-byte delta and a 2-byte mirror position) */
+  int64_t k_nnz_stored;   /* entries of K held in the blocked layout's nonzero blocks (all of K's
+                             nonzeros, or those on and right of the block diagonal) */
+  int32_t k_sym_stale;    /* level 0: 1 after amg_update_fine_values gave K values that are not
+                             symmetric; the FP64 kernels then use CSR copies of K and K^T */
 } amg_level_info;
 
 void amg_default_options(amg_options* opts);

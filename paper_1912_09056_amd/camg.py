@@ -24,6 +24,7 @@ CAMG_NOT_CONVERGED = 1
 PREC_FP64 = 0
 PREC_MIXED = 1
 PREC_MIXED_BF16 = 2
+SPMV_AUTO, SPMV_CSR, SPMV_BELL, SPMV_FULL = 0, 1, 2, 4
 KCLASS_SMOOTH_U = 1
 KCLASS_OPERATOR = 2
 KCLASS_ORTHO = 4
@@ -126,6 +127,9 @@ class amg_level_info(Structure):
         ("k_slots", c_int64),
         ("transfer_layout", c_int32),
         ("k_index_bytes", c_int32),
+        ("k_lower_blocks", c_int64),
+        ("k_nnz_stored", c_int64),
+        ("k_sym_stale", c_int32),
     ]
 
 
@@ -206,7 +210,9 @@ class AMGOptions:
     atilde: int = 0  # SIMPLEC lumping: 0 row sums of |K|, 1 diag(K), 2 nodal blocks (rotation-covariant)
     jacobi_diag: int = 0
     precision: int = PREC_FP64
-    spmv_format: int = 0  # 0 auto, 1 CSR, 2 sliced blocked-ELL
+    # 0 auto, 1 CSR, 2 sliced blocked-ELL; | 4 (SPMV_FULL): a K equal to its
+    # transpose stays in full blocked-ELL instead of symmetric storage
+    spmv_format: int = 0
     graphs: int = 1  # replay the V-cycle from a captured HIP graph
     jacobi_omega: float = 0.8
     simple_alpha: float = 0.8

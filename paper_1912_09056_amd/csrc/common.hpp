@@ -104,6 +104,16 @@ struct DCSR {
 // banded node numbering, as on structured meshes), bdel replaces bcol:
 //   bdel[p * 64 + lane] = block column - (64 s + lane),
 // two bytes per block instead of four.
+//
+// Symmetric storage (lptr set; K = K^T exactly): the positions above hold
+// only the blocks on or right of the block diagonal (column node >= row
+// node, always as 16-bit deltas).  The blocks left of it are not stored:
+// lower position q in [lptr[s], lptr[s+1]) of lane `lane` holds the word
+// w = lidx[q * 64 + lane], whose low 16 bits (signed) are the column node's
+// delta, j = 64 s + lane + delta (< the row's node), and whose high 16 bits
+// (signed) give the position of block (j, row node) in j's own slice as
+// slice_ptr[s] + (w >> 16); the kernel reads that block transposed from
+// lane j % 64 there.  Padding: high half INT16_MIN (no block).
 template <typename T>
 struct DBELL {
   int32_t n_nodes = 0, bs = 0, n_slices = 0;
@@ -115,6 +125,8 @@ struct DBELL {
   // FP32 views only: the values as bfloat16 words (the upper halves of the
   // FP32 words, rounded to nearest even) in place of val, same layout
   const uint16_t* val16 = nullptr;
+  const int32_t* lptr = nullptr;  // symmetric storage: lower positions per slice
+  const int32_t* lidx = nullptr;  // ... and their (delta, mirror position) words
 };
 
 }  // namespace camg

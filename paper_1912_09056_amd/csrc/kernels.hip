@@ -753,8 +753,88 @@ __device__ __forceinline__ T bell_row_impl(const DBELL<T>& A, const XT* __restri
   return acc;
 }
 
+// The same row with symmetric storage: the blocks left of the diagonal read
+// transposed from their mirror slots (column a of block (j, node) in lane
+// j % 64 of j's slice), then the stored blocks on and right of it.  The
+// lanes' blocks are visited in ascending column order, as in the full
+// layout, so both give the same sums.  Every value loads normally: a pass
+// reads each stored block a second time as a mirror block, a few thousand
+// slices later, from the caches.  The mirror loop has no branch (a padded
+// entry reads the lane's own first stored block and multiplies it by 0), so
+// the loads of successive positions overlap.
+template <typename T, typename XT, int BS, bool B16>
+__device__ __forceinline__ T bell_row_sym(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
+  const int bs = BS > 0 ? BS : A.bs;
+  const int bb = bs * bs;
+  const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
+  const int q0 = A.lptr[slice], q1 = A.lptr[slice + 1];
+  const int node = slice * 64 + lane;
+  const int base = node < A.n_nodes ? node : 0;
+  T acc = T(0);
+  // the index words of kChunk positions first (independent loads), then
+  // their mirror blocks; positions past q1 act as padding
+  constexpr int kChunk = 8;
+  constexpr int kPad = (int)0x80000000u;
+  for (int q = q0; q < q1; q += kChunk) {
+    int wd[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) wd[t] = q + t < q1 ? A.lidx[(int64_t)(q + t) * 64 + lane] : kPad;
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      const int rel = wd[t] >> 16;
+      const bool ok = rel != -32768;
+      const int j = ok ? base + (int)(int16_t)(wd[t] & 0xFFFF) : base;
+      const T m = ok ? T(1) : T(0);
+      const int64_t off = ((int64_t)(p0 + (ok ? rel : 0)) * bb + a) * 64 + (j & 63);
+      const XT* __restrict__ xc = x + (int64_t)j * bs;
+      if constexpr (B16) {
+        const uint16_t* __restrict__ v = A.val16 + off;
+        if (BS > 0) {
+#pragma unroll
+          for (int b = 0; b < BS; ++b) acc += ((T)bell_val16<false>(v + b * BS * 64) * m) * (T)xc[b];
+        } else {
+          for (int b = 0; b < bs; ++b) acc += ((T)bell_val16<false>(v + b * bs * 64) * m) * (T)xc[b];
+        }
+      } else {
+        const T* __restrict__ v = A.val + off;
+        if (BS > 0) {
+#pragma unroll
+          for (int b = 0; b < BS; ++b) acc += (bell_val<T, false>(v + b * BS * 64) * m) * (T)xc[b];
+        } else {
+          for (int b = 0; b < bs; ++b) acc += (bell_val<T, false>(v + b * bs * 64) * m) * (T)xc[b];
+        }
+      }
+    }
+  }
+#pragma unroll 2
+  for (int p = p0; p < p1; ++p) {
+    const int c = base + (int)A.bdel[(int64_t)p * 64 + lane];
+    const int64_t off = ((int64_t)p * bb + a * bs) * 64 + lane;
+    const XT* __restrict__ xc = x + (int64_t)c * bs;
+    if constexpr (B16) {
+      const uint16_t* __restrict__ v = A.val16 + off;
+      if (BS > 0) {
+#pragma unroll
+        for (int b = 0; b < BS; ++b) acc += (T)bell_val16<false>(v + b * 64) * (T)xc[b];
+      } else {
+        for (int b = 0; b < bs; ++b) acc += (T)bell_val16<false>(v + b * 64) * (T)xc[b];
+      }
+    } else {
+      const T* __restrict__ v = A.val + off;
+      if (BS > 0) {
+#pragma unroll
+        for (int b = 0; b < BS; ++b) acc += bell_val<T, false>(v + b * 64) * (T)xc[b];
+      } else {
+        for (int b = 0; b < bs; ++b) acc += bell_val<T, false>(v + b * 64) * (T)xc[b];
+      }
+    }
+  }
+  return acc;
+}
+
 template <typename T, typename XT, int BS, bool B16>
 __device__ __forceinline__ T bell_row_vals(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
+  if (A.lptr) return bell_row_sym<T, XT, BS, B16>(A, x, slice, lane, a);
   if (A.bdel) {
     if (A.stream) return bell_row_impl<T, XT, BS, true, true, B16>(A, x, slice, lane, a);
     return bell_row_impl<T, XT, BS, true, false, B16>(A, x, slice, lane, a);
@@ -1233,7 +1313,17 @@ __global__ void k_scatter_perm(const double* __restrict__ src, const int32_t* __
 __global__ void k_scatter_pos64(const double* __restrict__ src, const int64_t* __restrict__ pos,
                                 double* __restrict__ dst, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e < n) dst[pos[e]] = src[e];
+  if (e >= n) return;
+  const int64_t p = pos[e];
+  if (p >= 0) dst[p] = src[e];
+}
+
+// flag = 1 if some entry differs from its transpose partner (perm: entry ->
+// position of the mirrored entry in the same, symmetric, pattern)
+__global__ void k_check_symmetric(const double* __restrict__ v, const int32_t* __restrict__ perm, int64_t n,
+                                  int32_t* __restrict__ flag) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n && !(v[e] == v[perm[e]])) *flag = 1;
 }
 
 inline unsigned grid_for(int64_t rows, int rows_per_block) {
@@ -1847,6 +1937,12 @@ void scatter_perm(const double* src, const int32_t* perm, T* dst, int64_t nnz, h
 void scatter_pos64(const double* src, const int64_t* pos, double* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_scatter_pos64<<<grid_for(n, kBlock), kBlock, 0, s>>>(src, pos, dst, n);
+  CAMG_LAUNCHED();
+}
+
+void check_symmetric(const double* v, const int32_t* perm, int64_t n, int32_t* flag, hipStream_t s) {
+  if (n <= 0) return;
+  k_check_symmetric<<<grid_for(n, kBlock), kBlock, 0, s>>>(v, perm, n, flag);
   CAMG_LAUNCHED();
 }
 

@@ -242,5 +242,7 @@ template <typename T>
 void scatter_perm(const double* src, const int32_t* perm, T* dst, int64_t nnz, hipStream_t s);
 // dst[pos[e]] = src[e] with 64-bit positions (BELL value refresh).
 void scatter_pos64(const double* src, const int64_t* pos, double* dst, int64_t n, hipStream_t s);
+// flag = 1 when some v[e] != v[perm[e]] (the caller zeroes flag first)
+void check_symmetric(const double* v, const int32_t* perm, int64_t n, int32_t* flag, hipStream_t s);
 
 }  // namespace camg

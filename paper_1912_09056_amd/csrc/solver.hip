@@ -9,7 +9,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -155,8 +158,19 @@ struct HostBell {
   std::vector<int32_t> slice_ptr, bcol;
   std::vector<int16_t> bdel;  // bcol as deltas from the lane's node, when all fit in 16 bits
   std::vector<double> val;
-  std::vector<int64_t> pos;  // CSR entry -> index into val
+  std::vector<int64_t> pos;  // CSR entry -> index into val (-1: not stored, symmetric storage)
+  // symmetric storage (the DBELL comment in common.hpp): lower positions
+  bool sym = false;
+  std::vector<int32_t> lptr, lidx;
+  int64_t n_lower = 0;     // blocks left of the diagonal (read through their mirrors)
+  int64_t nnz_stored = 0;  // CSR entries in the stored blocks
 };
+
+// Whether a square CSR matrix equals its transpose exactly (pattern and
+// values); At is its transpose with sorted columns.
+static bool csr_symmetric(const HostCSR& A, const HostCSR& At) {
+  return A.rp == At.rp && A.ci == At.ci && A.v == At.v;
+}
 
 static HostBell make_bell(const HostCSR& A, int bs) {
   HostBell B;
@@ -245,6 +259,121 @@ static HostBell make_bell(const HostCSR& A, int bs) {
   return B;
 }
 
+// Symmetric storage of a square node-blocked CSR matrix that equals its
+// transpose: the blocks on and right of the block diagonal in the sliced
+// layout (16-bit deltas), the blocks left of it as (delta, mirror position)
+// pairs.  Returns a HostBell with sym = false when a delta or a mirror
+// offset does not fit 16 bits or a mirror block is missing.
+static HostBell make_bell_sym(const HostCSR& A, int bs) {
+  HostBell B;
+  B.bs = bs;
+  B.n_nodes = (int32_t)(A.nrows / bs);
+  B.n_slices = (B.n_nodes + 63) / 64;
+  const int nt = setup_threads();
+  const int bb = bs * bs;
+  // sorted distinct block columns per node, the number left of the diagonal,
+  // and each lane's offset into its slice's list
+  std::vector<std::vector<int32_t>> sl_cols((size_t)B.n_slices);
+  std::vector<std::vector<int32_t>> sl_cnt((size_t)B.n_slices), sl_low((size_t)B.n_slices),
+      sl_off((size_t)B.n_slices);
+  parallel_chunks(B.n_slices, nt, [&](int64_t sl, int) {
+    std::vector<int32_t> tmp;
+    auto& cols = sl_cols[(size_t)sl];
+    for (int32_t i = (int32_t)sl * 64; i < std::min(B.n_nodes, (int32_t)sl * 64 + 64); ++i) {
+      tmp.clear();
+      for (int a = 0; a < bs; ++a) {
+        const int64_t r = (int64_t)i * bs + a;
+        for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) tmp.push_back(A.ci[k] / bs);
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      sl_off[(size_t)sl].push_back((int32_t)cols.size());
+      cols.insert(cols.end(), tmp.begin(), tmp.end());
+      sl_cnt[(size_t)sl].push_back((int32_t)tmp.size());
+      sl_low[(size_t)sl].push_back((int32_t)(std::lower_bound(tmp.begin(), tmp.end(), i) - tmp.begin()));
+    }
+  });
+  B.slice_ptr.assign((size_t)B.n_slices + 1, 0);
+  B.lptr.assign((size_t)B.n_slices + 1, 0);
+  int64_t nblk = 0, nlow = 0;
+  for (int32_t sl = 0; sl < B.n_slices; ++sl) {
+    int32_t wu = 0, wl = 0;
+    for (size_t ln = 0; ln < sl_cnt[(size_t)sl].size(); ++ln) {
+      wu = std::max(wu, sl_cnt[(size_t)sl][ln] - sl_low[(size_t)sl][ln]);
+      wl = std::max(wl, sl_low[(size_t)sl][ln]);
+      nlow += sl_low[(size_t)sl][ln];
+    }
+    // at least one stored position: a padded mirror entry reads the lane's
+    // first stored block (and multiplies it by 0)
+    B.slice_ptr[sl + 1] = B.slice_ptr[sl] + std::max(wu, 1);
+    B.lptr[sl + 1] = B.lptr[sl] + wl;
+    nblk += (int64_t)sl_cols[(size_t)sl].size();
+  }
+  B.n_blocks = nblk;
+  B.n_lower = nlow;
+  const int64_t npos = B.slice_ptr[B.n_slices], nlpos = B.lptr[B.n_slices];
+  B.bdel.assign((size_t)(npos * 64), 0);
+  B.val.assign((size_t)(npos * 64 * bb), 0.0);
+  B.pos.assign((size_t)A.nnz(), -1);
+  const int32_t pad_word = (int32_t)((uint32_t)(uint16_t)INT16_MIN << 16);  // no block
+  B.lidx.assign((size_t)(nlpos * 64), pad_word);
+  std::atomic<bool> ok{true};
+  std::atomic<int64_t> stored{0};
+  parallel_chunks(B.n_slices, nt, [&](int64_t sl, int) {
+    const auto& cols = sl_cols[(size_t)sl];
+    const int64_t p0 = B.slice_ptr[sl], q0 = B.lptr[sl];
+    int64_t nst = 0;
+    for (int32_t lane = 0; lane < (int32_t)sl_cnt[(size_t)sl].size(); ++lane) {
+      const int32_t i = (int32_t)sl * 64 + lane;
+      const int32_t cnt = sl_cnt[(size_t)sl][(size_t)lane], low = sl_low[(size_t)sl][(size_t)lane];
+      const int32_t* b0 = cols.data() + sl_off[(size_t)sl][(size_t)lane];
+      for (int32_t k = low; k < cnt; ++k) {
+        const int64_t d = (int64_t)b0[k] - i;
+        if (d > 32767) ok = false;
+        else B.bdel[(size_t)((p0 + k - low) * 64 + lane)] = (int16_t)d;
+      }
+      for (int a = 0; a < bs; ++a) {
+        const int64_t r = (int64_t)i * bs + a;
+        for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+          const int32_t bc = A.ci[k] / bs, b = A.ci[k] % bs;
+          if (bc < i) continue;
+          const int64_t kk = std::lower_bound(b0 + low, b0 + cnt, bc) - (b0 + low);
+          const int64_t idx = ((p0 + kk) * bb + a * bs + b) * 64 + lane;
+          B.val[(size_t)idx] = A.v[k];
+          B.pos[(size_t)k] = idx;
+          ++nst;
+        }
+      }
+      // blocks left of the diagonal: block (i, c) = block (c, i)^T, stored
+      // in node c's upper list
+      for (int32_t k = 0; k < low; ++k) {
+        const int32_t c = b0[k];
+        const int64_t d = (int64_t)c - i;
+        const int32_t sc = c / 64, lc = c % 64;
+        const int32_t* c0 = sl_cols[(size_t)sc].data() + sl_off[(size_t)sc][(size_t)lc];
+        const int32_t clow = sl_low[(size_t)sc][(size_t)lc], ccnt = sl_cnt[(size_t)sc][(size_t)lc];
+        const int32_t* hit = std::lower_bound(c0 + clow, c0 + ccnt, i);
+        if (d < -32767 || hit == c0 + ccnt || *hit != i) {
+          ok = false;
+          continue;
+        }
+        const int64_t rel = (int64_t)B.slice_ptr[sc] + (hit - (c0 + clow)) - p0;
+        if (rel < -32767 || rel > 32767) {
+          ok = false;
+          continue;
+        }
+        B.lidx[(size_t)((q0 + k) * 64 + lane)] =
+            (int32_t)(((uint32_t)(uint16_t)(int16_t)rel << 16) | (uint32_t)(uint16_t)(int16_t)d);
+      }
+    }
+    stored += nst;
+  });
+  B.nnz_stored = stored;
+  B.sym = ok;
+  if (!B.sym) return HostBell{};
+  return B;
+}
+
 struct DevBell {
   int32_t n_nodes = 0, bs = 0, n_slices = 0;
   DBuf<int32_t> slice_ptr, bcol;
@@ -252,6 +381,7 @@ struct DevBell {
   DBuf<double> v64;
   DBuf<float> v32;
   DBuf<uint16_t> v16;  // bfloat16 words in place of v32 (fine-level K with CAMG_PREC_MIXED_BF16)
+  DBuf<int32_t> lptr, lidx;  // symmetric storage: lower positions
   template <typename T>
   DBELL<T> view() const {
     DBELL<T> d;
@@ -261,6 +391,8 @@ struct DevBell {
     d.slice_ptr = slice_ptr.p;
     d.bcol = bcol.p;
     d.bdel = bdel.p;
+    d.lptr = lptr.p;
+    d.lidx = lidx.p;
     if constexpr (sizeof(T) == 8) {
       d.val = reinterpret_cast<const T*>(v64.p);
       d.stream = 1;
@@ -285,6 +417,10 @@ static void upload_bell(DevBell& D, const HostBell& H, bool f64, bool f32, hipSt
   D.slice_ptr.upload(H.slice_ptr, s);
   if (!H.bdel.empty()) D.bdel.upload(H.bdel, s);
   else D.bcol.upload(H.bcol, s);
+  if (H.sym) {
+    D.lptr.upload(H.lptr, s);
+    D.lidx.upload(H.lidx, s);
+  }
   if (f64) D.v64.upload(H.val, s);
   if (f32 && b16) {
     std::vector<uint16_t> v16(H.val.size());
@@ -331,8 +467,13 @@ struct DevLevel {
   DBuf<int32_t> g_nodes;  // nodal sweep: nodes with a nonempty G row (the back-substitution's support)
   int32_t n_g_nodes = 0;
   bool bell = false;   // K and K^T in sliced blocked-ELL layout
+  // sym: K = K^T and Kb holds it in symmetric storage, which also serves
+  // the transposed kernels (KTb stays empty).  sym_stale: level 0 after an
+  // update of K's values that are no longer symmetric; its FP64 kernels then
+  // use the CSR copies (the FP32 hierarchy keeps the values it was built on).
+  bool sym = false, sym_stale = false;
   DevBell Kb, KTb;
-  int64_t k_blocks = 0, k_slots = 0;
+  int64_t k_blocks = 0, k_slots = 0, k_lower = 0, k_nnz_stored = 0;
   DBuf<int32_t> g_rows;
   int32_t n_g_rows = 0;
   int sg_K = 16, sg_R = 16, sg_P = 8;
@@ -348,6 +489,16 @@ struct DevLevel {
   LevelVecs<double> v64;
   LevelVecs<float> v32;
   int64_t n() const { return n_u + n_l; }
+  // whether the kernels of precision T use the blocked-ELL copies of K
+  template <typename T>
+  bool bell_for() const {
+    return bell && !(sizeof(T) == 8 && sym_stale);
+  }
+  // blocked-ELL view of K or K^T (the symmetric storage serves both)
+  template <typename T>
+  DBELL<T> kview(bool trans) const {
+    return (trans && !sym ? KTb : Kb).template view<T>();
+  }
 };
 
 template <>
@@ -488,7 +639,8 @@ struct amg_handle {
   std::vector<DevLevel> lev;
   std::vector<int32_t> perm_K, perm_G, perm_B, perm_C;
   DBuf<int32_t> d_perm_K, d_perm_G, d_perm_B, d_perm_C;
-  DBuf<int64_t> d_bpos_K, d_bpos_KT;  // level-0 K entry -> BELL slot of K / K^T
+  DBuf<int64_t> d_bpos_K, d_bpos_KT;  // level-0 K entry -> BELL slot of K / K^T (-1: not stored)
+  DBuf<int32_t> d_asym;               // symmetric storage: flag set by the symmetry check of an update
   int64_t n = 0, n_u = 0, n_l = 0;
   // Krylov workspace
   int m_alloc = 0;
@@ -659,23 +811,39 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
     {
       const int64_t nodes = H.n_u() / H.bs_u;
       const int64_t slices = (nodes + 63) / 64;
-      const int fmt = h.opts.spmv_format;
+      const int fmt = h.opts.spmv_format & ~CAMG_SPMV_FULL;
+      const bool full = (h.opts.spmv_format & CAMG_SPMV_FULL) != 0;
       D.bell = (fmt == CAMG_SPMV_BELL) || (fmt == CAMG_SPMV_AUTO && slices >= 512);
       if (D.bell && H.bs_u > 0 && H.n_u() % H.bs_u == 0) {
-        HostBell hb = make_bell(H.K, H.bs_u);
-        HostBell hbt = make_bell(KT, H.bs_u);
-        if (l == 0) {
-          std::vector<int64_t> posT((size_t)H.K.nnz());
-          parallel_for(H.K.nnz(), [&](int64_t k0, int64_t k1) {
-            for (int64_t k = k0; k < k1; ++k) posT[(size_t)k] = hbt.pos[(size_t)h.perm_K[(size_t)k]];
-          });
-          h.d_bpos_K.upload(hb.pos, s);
-          h.d_bpos_KT.upload(posT, s);
-          CAMG_HIP(hipStreamSynchronize(s));
-        }
         const bool b16 = l == 0 && h.opts.precision == CAMG_PREC_MIXED_BF16;
-        upload_bell(D.Kb, hb, f64, f32, s, b16);
-        upload_bell(D.KTb, hbt, f64, f32, s, b16);
+        HostBell hb;
+        if (!full && csr_symmetric(H.K, KT)) hb = make_bell_sym(H.K, H.bs_u);
+        D.sym = hb.sym;
+        if (D.sym) {
+          if (l == 0) {
+            h.d_bpos_K.upload(hb.pos, s);
+            h.d_asym.alloc(1);
+            CAMG_HIP(hipStreamSynchronize(s));
+          }
+          upload_bell(D.Kb, hb, f64, f32, s, b16);
+          D.k_lower = hb.n_lower;
+          D.k_nnz_stored = hb.nnz_stored;
+        } else {
+          hb = make_bell(H.K, H.bs_u);
+          HostBell hbt = make_bell(KT, H.bs_u);
+          if (l == 0) {
+            std::vector<int64_t> posT((size_t)H.K.nnz());
+            parallel_for(H.K.nnz(), [&](int64_t k0, int64_t k1) {
+              for (int64_t k = k0; k < k1; ++k) posT[(size_t)k] = hbt.pos[(size_t)h.perm_K[(size_t)k]];
+            });
+            h.d_bpos_K.upload(hb.pos, s);
+            h.d_bpos_KT.upload(posT, s);
+            CAMG_HIP(hipStreamSynchronize(s));
+          }
+          upload_bell(D.Kb, hb, f64, f32, s, b16);
+          upload_bell(D.KTb, hbt, f64, f32, s, b16);
+          D.k_nnz_stored = H.K.nnz();
+        }
         D.k_blocks = hb.n_blocks;
         D.k_slots = (int64_t)hb.slice_ptr.back() * 64;
       } else {
@@ -683,7 +851,7 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
       }
     }
     // coarse levels: node-blocked copies of K and K^T for the row dots
-    if (!D.bell && l > 0 && h.opts.spmv_format == CAMG_SPMV_AUTO &&
+    if (!D.bell && l > 0 && (h.opts.spmv_format & ~CAMG_SPMV_FULL) == CAMG_SPMV_AUTO &&
         !(coarsest && h.opts.coarse_solver == CAMG_COARSE_LU)) {
       upload_rowblock(D.K, H.K, H.bs_u, f64, f32, s);
       upload_rowblock(D.KT, KT, H.bs_u, f64, f32, s);
@@ -829,8 +997,8 @@ static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const 
     // prediction: t = b_u - K z_u - G z_l (t = b_u from zero), w = J(t), zn_u = z_u + w
     const T* t = bu;
     bool zn_done = false;
-    if (!first && D.bell) {
-      smooth_u_bell_nodal<T>(D.Kb.view<T>(), D.G.view<T>(), zu, zl, bu, M, om, znu, nj > 1 ? V.aux1.p : nullptr, wa,
+    if (!first && D.bell_for<T>()) {
+      smooth_u_bell_nodal<T>(D.kview<T>(false), D.G.view<T>(), zu, zl, bu, M, om, znu, nj > 1 ? V.aux1.p : nullptr, wa,
                              nu, s);
       t = V.aux1.p;
       zn_done = nj == 1;
@@ -843,8 +1011,8 @@ static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const 
       node_apply<T>(M, t, om, nullptr, nullptr, wa, nu, bs, false, s);
     }
     for (int k = 1; k < nj; ++k) {
-      if (D.bell)
-        blk_spmv_bell<T>(D.Kb.view<T>(), none, none, none, wa, nullptr, t, nullptr, tr, nullptr, nu, 0, 1, s);
+      if (D.bell_for<T>())
+        blk_spmv_bell<T>(D.kview<T>(false), none, none, none, wa, nullptr, t, nullptr, tr, nullptr, nu, 0, 1, s);
       else
         blk_spmv<T>(D.K.view<T>(), none, none, none, wa, nullptr, t, nullptr, tr, nullptr, nu, 0, 1, D.sg_K, s);
       node_apply<T>(M, tr, om, wa, wb, nullptr, nu, bs, false, s);
@@ -862,8 +1030,8 @@ static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const 
     if (first) zero_vec<T>(const_cast<T*>(zl), nl, s);
     const T* su = bu;
     if (!first) {
-      if (D.bell)
-        tsmooth_u_bell<T>(D.KTb.view<T>(), D.BT.view<T>(), zu, zl, bu, V.aux1.p, nu, s);
+      if (D.bell_for<T>())
+        tsmooth_u_bell<T>(D.kview<T>(true), D.BT.view<T>(), zu, zl, bu, V.aux1.p, nu, s);
       else
         tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.aux1.p, nu, false, D.sg_K, s);
       su = V.aux1.p;
@@ -888,8 +1056,8 @@ static void sweep_nodal(amg_handle& h, int l, bool transpose, const T* b, const 
       T* tk = V.aux1.p == su ? V.su.p : V.aux1.p;  // s_u is no longer needed
       wb = (tk == V.su.p) ? V.aux1.p : V.su.p;
       for (int k = 1; k < nj; ++k) {
-        if (D.bell)
-          blk_spmv_bell<T>(D.KTb.view<T>(), none, none, none, wa, nullptr, t, nullptr, tk, nullptr, nu, 0, 1, s);
+        if (D.bell_for<T>())
+          blk_spmv_bell<T>(D.kview<T>(true), none, none, none, wa, nullptr, t, nullptr, tk, nullptr, nu, 0, 1, s);
         else
           blk_spmv<T>(D.KT.view<T>(), none, none, none, wa, nullptr, t, nullptr, tk, nullptr, nu, 0, 1, D.sg_K, s);
         node_apply<T>(M, tk, om, wa, wb, nullptr, nu, bs, true, s);
@@ -950,8 +1118,8 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
   if (!transpose) {
     {
       ProfScope ps(first ? nullptr : pp, CAMG_KCLASS_SMOOTH_U, s);
-      if (D.bell && !first)
-        smooth_u_bell<T>(D.Kb.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, keep_w ? V.aux1.p : nullptr,
+      if (D.bell_for<T>() && !first)
+        smooth_u_bell<T>(D.kview<T>(false), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, keep_w ? V.aux1.p : nullptr,
                          keep_w ? V.aux2.p : nullptr, nu, s);
       else
         smooth_u<T>(D.K.view<T>(), D.G.view<T>(), zu, zl, bu, V.jinv.p, om, znu, keep_w ? V.aux1.p : nullptr,
@@ -960,8 +1128,8 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
     T* wa = V.aux2.p;
     T* wb = V.su.p;
     for (int k = 1; k < nj; ++k) {
-      if (D.bell)
-        jacobi_extra_bell<T>(D.Kb.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1,
+      if (D.bell_for<T>())
+        jacobi_extra_bell<T>(D.kview<T>(false), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1,
                              nu, s);
       else
         jacobi_extra<T>(D.K.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
@@ -979,8 +1147,8 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
     const T* su = first ? bu : V.su.p;
     if (!first) {
       ProfScope ps(pp, CAMG_KCLASS_SMOOTH_U, s);
-      if (D.bell)
-        tsmooth_u_bell<T>(D.KTb.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, s);
+      if (D.bell_for<T>())
+        tsmooth_u_bell<T>(D.kview<T>(true), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, s);
       else
         tsmooth_u<T>(D.KT.view<T>(), D.BT.view<T>(), zu, zl, bu, V.su.p, nu, false, D.sg_K, s);
     }
@@ -992,8 +1160,8 @@ static void sweep(amg_handle& h, int l, bool transpose, const T* b, const T* z, 
     T* wa = V.aux2.p;
     T* wb = V.r.p;  // r is free during a sweep
     for (int k = 1; k < nj; ++k) {
-      if (D.bell)
-        jacobi_extra_bell<T>(D.KTb.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu,
+      if (D.bell_for<T>())
+        jacobi_extra_bell<T>(D.kview<T>(true), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu,
                              k == nj - 1, nu, s);
       else
         jacobi_extra<T>(D.KT.view<T>(), wa, V.aux1.p, V.jinv.p, om, wb, first ? nullptr : zu, znu, k == nj - 1, nu,
@@ -1039,12 +1207,12 @@ static T* vcycle_level(amg_handle& h, int l, bool transpose, hipStream_t s) {
   if (first) zero_vec<T>(zc, D.n(), s);
   {
     ProfScope ps(l == 0 ? &h.prof : nullptr, CAMG_KCLASS_RESIDUAL, s);
-    if (D.bell) {
+    if (D.bell_for<T>()) {
       if (!transpose)
-        blk_spmv_bell<T>(D.Kb.view<T>(), D.G.view<T>(), D.B.view<T>(), D.C.view<T>(), zc, zc + nu, V.b.p, V.b.p + nu,
+        blk_spmv_bell<T>(D.kview<T>(false), D.G.view<T>(), D.B.view<T>(), D.C.view<T>(), zc, zc + nu, V.b.p, V.b.p + nu,
                          V.r.p, V.r.p + nu, nu, nl, 1, s);
       else
-        blk_spmv_bell<T>(D.KTb.view<T>(), D.BT.view<T>(), D.GT.view<T>(), D.CT.view<T>(), zc, zc + nu, V.b.p,
+        blk_spmv_bell<T>(D.kview<T>(true), D.BT.view<T>(), D.GT.view<T>(), D.CT.view<T>(), zc, zc + nu, V.b.p,
                          V.b.p + nu, V.r.p, V.r.p + nu, nu, nl, 1, s);
     } else if (!transpose)
       blk_spmv<T>(D.K.view<T>(), D.G.view<T>(), D.B.view<T>(), D.C.view<T>(), zc, zc + nu, V.b.p, V.b.p + nu, V.r.p,
@@ -1069,6 +1237,16 @@ static T* vcycle_level(amg_handle& h, int l, bool transpose, hipStream_t s) {
     std::swap(zc, zx);
   }
   return zc;
+}
+
+static void drop_vcycle_graphs(amg_handle& h) {
+  for (int t = 0; t < 2; ++t) {
+    if (h.vexec[t]) (void)hipGraphExecDestroy(h.vexec[t]);
+    if (h.vgraph[t]) (void)hipGraphDestroy(h.vgraph[t]);
+    h.vexec[t] = nullptr;
+    h.vgraph[t] = nullptr;
+    h.vout[t] = nullptr;
+  }
 }
 
 // The V-cycle's kernel sequence and buffers are fixed for a handle, so with
@@ -1190,12 +1368,12 @@ static void apply_op(amg_handle& h, bool transpose, const double* x, const doubl
   const int nu = (int)D.n_u, nl = (int)D.n_l;
   ProfScope ps(&h.prof, CAMG_KCLASS_OPERATOR, s);
   const int mode = b ? 1 : 0;
-  if (D.bell) {
+  if (D.bell_for<double>()) {
     if (!transpose)
-      blk_spmv_bell<double>(D.Kb.view<double>(), D.G.view<double>(), D.B.view<double>(), D.C.view<double>(), x,
+      blk_spmv_bell<double>(D.kview<double>(false), D.G.view<double>(), D.B.view<double>(), D.C.view<double>(), x,
                             x + nu, b, b ? b + nu : nullptr, y, y + nu, nu, nl, mode, s);
     else
-      blk_spmv_bell<double>(D.KTb.view<double>(), D.BT.view<double>(), D.GT.view<double>(), D.CT.view<double>(), x,
+      blk_spmv_bell<double>(D.kview<double>(true), D.BT.view<double>(), D.GT.view<double>(), D.CT.view<double>(), x,
                             x + nu, b, b ? b + nu : nullptr, y, y + nu, nu, nl, mode, s);
   } else if (!transpose)
     blk_spmv<double>(D.K.view<double>(), D.G.view<double>(), D.B.view<double>(), D.C.view<double>(), x, x + nu, b,
@@ -1269,10 +1447,10 @@ static int gmres(amg_handle& h, bool transpose, const double* b, double* x, cons
       const double* scale = j ? h.out.p + 2 : nullptr;
       if (mixed) arnoldi_prep<float>(h.w.p, scale, vj, D0.v32.b.p, n, s);
       else arnoldi_prep<double>(h.w.p, scale, vj, D0.v64.b.p, n, s);
-      if (D0.bell) {
+      if (D0.bell_for<double>()) {
         // the FP64 operator reads the V-cycle output directly and stores z_j
         const int nu0 = (int)D0.n_u, nl0 = (int)D0.n_l;
-        const DBELL<double> Kx = transpose ? D0.KTb.view<double>() : D0.Kb.view<double>();
+        const DBELL<double> Kx = D0.kview<double>(transpose);
         const DCSR<double> A12 = transpose ? D0.BT.view<double>() : D0.G.view<double>();
         const DCSR<double> A21 = transpose ? D0.GT.view<double>() : D0.B.view<double>();
         const DCSR<double> A22 = transpose ? D0.CT.view<double>() : D0.C.view<double>();
@@ -1479,7 +1657,8 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   if (o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.jacobi_sweeps < 1 ||
       o.precision < CAMG_PREC_FP64 || o.precision > CAMG_PREC_MIXED_BF16 || o.atilde < 0 || o.atilde > 2 ||
       (o.atilde == CAMG_ATILDE_NODAL && o.jacobi_diag != CAMG_JACOBI_ATILDE) ||
-      o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 2 || o.graphs < 0 ||
+      o.jacobi_diag < 0 || o.jacobi_diag > 1 || o.spmv_format < 0 || o.spmv_format > 6 ||
+      (o.spmv_format & 3) == 3 || o.spmv_format == (CAMG_SPMV_CSR | CAMG_SPMV_FULL) || o.graphs < 0 ||
       o.graphs > 1 || o.prolongator < 0 || o.prolongator > 1 || o.schur < 0 || o.schur > 2 || o.schur_sweeps < 1 ||
       o.schur_sweeps > 64 || !(o.sa_omega > 0.0) || !std::isfinite(o.sa_omega) || o.coarse_solver < 0 ||
       o.coarse_solver > 1 || o.coarse_sweeps < 1 || o.coarse_sweeps > 64 || o.smoother < 0 || o.smoother > 2 ||
@@ -1688,12 +1867,18 @@ int amg_level_info_get(const amg_handle* h, int level, amg_level_info* out) {
     out->k_slots = 0;
     out->transfer_layout = -1;
     out->k_index_bytes = 0;
+    out->k_lower_blocks = 0;
+    out->k_nnz_stored = 0;
+    out->k_sym_stale = 0;
     if (!h->lev.empty()) {
       const DevLevel& D = h->lev[level];
-      out->k_layout = D.bell ? 1 : (D.K.bs > 0 ? 2 : 0);
+      out->k_layout = D.bell ? (D.sym ? 3 : 1) : (D.K.bs > 0 ? 2 : 0);
       out->k_index_bytes = D.bell ? (D.Kb.bdel.p ? 2 : 4) : (D.K.bs > 0 ? 4 : 0);
       out->k_blocks = D.bell ? D.k_blocks : (D.K.bs > 0 ? (int64_t)D.K.bcol.n : 0);
       out->k_slots = D.k_slots;
+      out->k_lower_blocks = D.k_lower;
+      out->k_nnz_stored = D.bell ? D.k_nnz_stored : 0;
+      out->k_sym_stale = D.sym_stale ? 1 : 0;
       if (level + 1 < (int)h->lev.size()) out->transfer_layout = D.agg_ok ? 1 : 0;
     }
     return CAMG_OK;
@@ -1772,8 +1957,23 @@ int amg_update_fine_values(amg_handle* h, const double* K_val, const double* G_v
       scatter_perm<double>(it.src, it.perm->p, it.MT->v64.p, it.M->nnz, s);
     }
     if (K_val && D.bell && D.K.nnz) {
-      scatter_pos64(K_val, h->d_bpos_K.p, D.Kb.v64.p, D.K.nnz, s);
-      scatter_pos64(K_val, h->d_bpos_KT.p, D.KTb.v64.p, D.K.nnz, s);
+      if (D.sym) {
+        // the symmetric storage keeps one block of each mirror pair: it stays
+        // in use only while the new values are symmetric too
+        CAMG_HIP(hipMemsetAsync(h->d_asym.p, 0, sizeof(int32_t), s));
+        check_symmetric(K_val, h->d_perm_K.p, D.K.nnz, h->d_asym.p, s);
+        int32_t asym = 0;
+        CAMG_HIP(hipMemcpyAsync(&asym, h->d_asym.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CAMG_HIP(hipStreamSynchronize(s));
+        const bool stale = asym != 0;
+        if (!stale) scatter_pos64(K_val, h->d_bpos_K.p, D.Kb.v64.p, D.K.nnz, s);
+        // an FP64 V-cycle switches its level-0 kernels: capture it again
+        if (stale != D.sym_stale && h->opts.precision == CAMG_PREC_FP64) drop_vcycle_graphs(*h);
+        D.sym_stale = stale;
+      } else {
+        scatter_pos64(K_val, h->d_bpos_K.p, D.Kb.v64.p, D.K.nnz, s);
+        scatter_pos64(K_val, h->d_bpos_KT.p, D.KTb.v64.p, D.K.nnz, s);
+      }
     }
     return CAMG_OK;
   });

@@ -446,7 +446,7 @@ def test_robust_options_three_level(fmt):
     r = np.random.default_rng(12).standard_normal(prob.n)
     for prec, tol in ((0, 1e-12), (1, 2e-5)):
         s = _solver(prob, precision=prec, fmt=fmt, **kw, **ROBUST_LIB)
-        assert s.level_info(1)["k_layout"] == {1: 0, 2: 1}[fmt]
+        assert s.level_info(1)["k_layout"] in {1: (0,), 2: (1, 3)}[fmt]
         for tr in (False, True):
             z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
             assert _rel(z, oracle_vcycle(lv, r, oopts, transpose=tr)) < tol, (prec, tr)
@@ -1047,10 +1047,12 @@ def test_blocked_ell_block_index_widths():
     shuffled = _permute_nodes(prob, 12)
     kw = dict(max_levels=2)
     r = np.random.default_rng(6).standard_normal(prob.n)
-    for p, width in ((prob, 2), (shuffled, 4)):
+    # banded: symmetric storage (K = K^T, 16-bit deltas); shuffled: the deltas
+    # do not fit, so the full layout with 32-bit columns
+    for p, width, layout in ((prob, 2, 3), (shuffled, 4, 1)):
         s = _solver(p, **kw)
         info = s.level_info(0)
-        assert info["k_layout"] == 1 and info["k_index_bytes"] == width, info
+        assert info["k_layout"] == layout and info["k_index_bytes"] == width, info
         lv = build_hierarchy(p, OracleOptions(**kw))
         for tr in (False, True):
             z = s.vcycle(torch.from_numpy(r), transpose=tr).cpu().numpy()
@@ -1093,3 +1095,69 @@ def test_bf16_fine_level_storage(name, levels):
     assert i16["converged"] and res <= 1.0001e-8
     assert i16["iters"] <= i32["iters"] + 3
     assert err < 1e-7
+
+
+@pytest.mark.parametrize("name,levels", [("contact3d_6", 2), ("contact3d_40", 4)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_symmetric_storage_matches_full_layout(name, levels, prec):
+    """K = K^T exactly, so the blocked-ELL kernels keep only the blocks on and
+    right of the block diagonal and read the others transposed from their
+    mirrors.  Each row still visits its blocks in ascending column order, so
+    the V-cycle (both directions), the FP64 operator and the whole solve
+    equal those of the full layout bit for bit, in every precision."""
+    prob = make_workload(name)
+    kw = dict(max_levels=levels)
+    ssym = _solver(prob, precision=prec, fmt=2, **kw)
+    sful = _solver(prob, precision=prec, fmt=2 | 4, **kw)  # CAMG_SPMV_BELL | CAMG_SPMV_FULL
+    i_sym, i_ful = ssym.level_info(0), sful.level_info(0)
+    assert i_sym["k_layout"] == 3 and i_ful["k_layout"] == 1, (i_sym, i_ful)
+    assert i_sym["k_blocks"] == i_ful["k_blocks"]
+    assert 0 < i_sym["k_lower_blocks"] < i_sym["k_blocks"] / 2
+    assert i_ful["k_nnz_stored"] == prob.K.nnz and i_sym["k_nnz_stored"] < prob.K.nnz
+    rng = np.random.default_rng(44)
+    for tr in (False, True):
+        r = torch.from_numpy(rng.standard_normal(prob.n)).cuda()
+        a = ssym.vcycle(r, transpose=tr).cpu().numpy()
+        b = sful.vcycle(r, transpose=tr).cpu().numpy()
+        assert np.array_equal(a, b), (tr, _rel(a, b))
+        a = ssym.apply_operator(r, transpose=tr).cpu().numpy()
+        b = sful.apply_operator(r, transpose=tr).cpu().numpy()
+        assert np.array_equal(a, b), (tr, _rel(a, b))
+    bb = torch.from_numpy(prob.b).cuda()
+    xs, fs = ssym.solve(bb, rtol=1e-8)
+    xf, ff = sful.solve(bb, rtol=1e-8)
+    print(f"[sym] {name} prec={prec}: iterations {fs['iters']} / {ff['iters']}", flush=True)
+    assert fs["converged"] and fs["iters"] == ff["iters"]
+    assert np.array_equal(xs.cpu().numpy(), xf.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_symmetric_storage_after_nonsymmetric_update(prec):
+    """New level-0 K values that are not symmetric cannot live in the
+    symmetric storage: the FP64 operator (and an FP64 V-cycle) switch to the
+    CSR copies, which hold the new values; symmetric values switch back."""
+    prob = make_workload("contact3d_6")
+    s = _solver(prob, precision=prec, fmt=2, max_levels=2)
+    assert s.level_info(0)["k_layout"] == 3
+    K1 = prob.K.tocsr()
+    K2 = K1.copy()
+    K2.data = K2.data * (1.0 + 0.2 * np.random.default_rng(5).random(K2.nnz))
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(prob.n)
+    xt = torch.from_numpy(x).cuda()
+    for K, stale in ((K2, 1), (K1, 0), (K2, 1), (K1, 0)):
+        s.update_fine_values(K_val=torch.from_numpy(K.data.copy()).cuda())
+        assert s.level_info(0)["k_sym_stale"] == stale
+        A = sp.bmat([[K, prob.G], [prob.B, prob.C]]).tocsr()
+        for tr in (False, True):
+            y = s.apply_operator(xt, transpose=tr).cpu().numpy()
+            ref = (A.T if tr else A) @ x
+            assert _rel(y, ref) < 1e-14, (stale, tr)
+        xx, fi = s.solve(torch.from_numpy(prob.b).cuda(), rtol=1e-10)
+        res = np.linalg.norm(prob.b - A @ xx.cpu().numpy()) / np.linalg.norm(prob.b)
+        assert fi["converged"] and res <= 1.0001e-10, (stale, res)
+    # back on the symmetric values: the V-cycle equals a fresh solver's
+    fresh = _solver(prob, precision=prec, fmt=2, max_levels=2)
+    r = torch.from_numpy(rng.standard_normal(prob.n)).cuda()
+    for tr in (False, True):
+        assert np.array_equal(s.vcycle(r, transpose=tr).cpu().numpy(), fresh.vcycle(r, transpose=tr).cpu().numpy())
