@@ -120,6 +120,17 @@ def _assemble_body(nelem, axes, lam_e, mu_e, Klam, Kmu):
             valid[:, o] &= (c >= 0) & (c < nn[k])
             lin = lin + dvec[k] * stride[k]
         nbr[:, o] = lin
+    # exact symmetry: the loop above reaches block (i, j) and block (j, i)^T
+    # through different element orders, so they differ by rounding; both
+    # become their mean (offset o and n_off - 1 - o are mirrors)
+    sym = np.empty_like(blocks)
+    for o in range(n_off):
+        v = valid[:, o]
+        mirror = np.swapaxes(blocks[nbr[v, o], n_off - 1 - o], -1, -2)
+        sym[v, o] = (blocks[v, o] + mirror) * 0.5
+        sym[~v, o] = 0.0
+    blocks = sym
+    del sym
     # row (node, a) holds, for each valid offset o (increasing column), d columns
     vals = np.transpose(blocks, (0, 2, 1, 3))  # node, a, o, b
     mask = np.broadcast_to(valid[:, None, :, None], vals.shape)
@@ -410,7 +421,6 @@ def make_contact_problem(
         Mx.sum_duplicates()
         mats.append(Mx)
     K, G, Bm, Cm = mats
-    K = exact_symmetric(K)
 
     # right-hand side
     top_dofs = slave_top_nodes * dim + last
