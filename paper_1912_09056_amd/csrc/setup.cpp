@@ -285,6 +285,47 @@ void tentative(int64_t n_rows, int n_ns, const std::vector<double>& ns, const st
   }
 }
 
+// Whether a square CSR matrix (sorted columns) equals its transpose bit for
+// bit: every entry has a mirror entry holding the same value.
+bool csr_equals_transpose(const HostCSR& A) {
+  if (A.nrows != A.ncols) return false;
+  std::atomic<bool> ok{true};
+  parallel_for(A.nrows, [&](int64_t r0, int64_t r1) {
+    for (int64_t i = r0; i < r1 && ok; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int32_t j = A.ci[k];
+        const auto b = A.ci.begin() + A.rp[j], e = A.ci.begin() + A.rp[j + 1];
+        const auto it = std::lower_bound(b, e, (int32_t)i);
+        if (it == e || *it != (int32_t)i || !(A.v[(size_t)(it - A.ci.begin())] == A.v[(size_t)k])) {
+          ok = false;
+          break;
+        }
+      }
+  });
+  return ok;
+}
+
+// Mirrored entries of a square CSR matrix with a symmetric pattern replaced
+// by their mean, (A_ij + A_ji) / 2, the same number for both: the matrix
+// then equals its transpose bit for bit.  Each pair is written by the row of
+// its upper entry.
+void symmetrize_values(HostCSR& A) {
+  parallel_for(A.nrows, [&](int64_t r0, int64_t r1) {
+    for (int64_t i = r0; i < r1; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int32_t j = A.ci[k];
+        if (j <= i) continue;
+        const auto b = A.ci.begin() + A.rp[j], e = A.ci.begin() + A.rp[j + 1];
+        const auto it = std::lower_bound(b, e, (int32_t)i);
+        if (it == e || *it != (int32_t)i) continue;
+        const size_t m = (size_t)(it - A.ci.begin());
+        const double v = (A.v[(size_t)k] + A.v[m]) * 0.5;
+        A.v[(size_t)k] = v;
+        A.v[m] = v;
+      }
+  });
+}
+
 // R A P on the symbolic pattern.  Consecutive rows of R with identical
 // column sets (the rows of one aggregate) share one pass over A P; groups
 // are independent and run on the setup threads.
@@ -852,6 +893,14 @@ HostLevel coarsen(HostLevel& L, const SetupOptions& opt) {
   {
     PhaseTimer pt("galerkin");
     Cn.K = galerkin(Ru, L.K, L.P_u);
+    // with K = K^T and R = P^T the coarse K is symmetric in exact arithmetic,
+    // but its sums reach mirrored entries in different orders: restore the
+    // symmetry bit for bit (a change of rounding size), so the coarse level
+    // can use the symmetric blocked-ELL storage too
+    if (L.k_symmetric) {
+      symmetrize_values(Cn.K);
+      Cn.k_symmetric = csr_equals_transpose(Cn.K);
+    }
     Cn.G = galerkin(Ru, L.G, L.P_l);
     Cn.B = galerkin(Rl, L.B, L.P_u);
     Cn.C = galerkin(Rl, L.C, L.P_l);
@@ -898,6 +947,7 @@ HostCSR transpose(const HostCSR& A, std::vector<int32_t>* perm) {
 }
 
 void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt) {
+  levels[0].k_symmetric = csr_equals_transpose(levels[0].K);
   while ((int)levels.size() < opt.max_levels && levels.back().n() > opt.max_coarse_rows) {
     HostLevel nxt = coarsen(levels.back(), opt);
     if (nxt.n() >= levels.back().n()) {

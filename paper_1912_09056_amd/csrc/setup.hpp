@@ -104,6 +104,7 @@ struct PhaseTimer {
 
 struct HostLevel {
   HostCSR K, G, B, C;
+  bool k_symmetric = false;        // K equals its transpose bit for bit
   int bs_u = 0, bs_l = 0;          // dofs per displacement node / multiplier node
   int n_ns_u = 0, n_ns_l = 0;      // null-space columns (next level's block sizes)
   std::vector<uint8_t> slave_node, master_node;  // per displacement node
