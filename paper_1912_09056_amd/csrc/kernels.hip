@@ -832,6 +832,75 @@ __device__ __forceinline__ T bell_row_sym(const DBELL<T>& A, const XT* __restric
   return acc;
 }
 
+// Symmetric storage, one node per lane: a thread accumulates all BS rows of
+// its node, so a slice's x entries, index words and mirror blocks are loaded
+// once instead of once per row wave.  Per row the same products in the same
+// order as bell_row_sym.
+template <typename T, typename XT, int BS, bool B16>
+__device__ __forceinline__ void bell_node_sym_impl(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane,
+                                                   T (&acc)[BS]) {
+  constexpr int bb = BS * BS;
+  const int p0 = A.slice_ptr[slice], p1 = A.slice_ptr[slice + 1];
+  const int q0 = A.lptr[slice], q1 = A.lptr[slice + 1];
+  const int node = slice * 64 + lane;
+  const int base = node < A.n_nodes ? node : 0;
+#pragma unroll
+  for (int a = 0; a < BS; ++a) acc[a] = T(0);
+  constexpr int kChunk = 4;
+  constexpr int kPad = (int)0x80000000u;
+  for (int q = q0; q < q1; q += kChunk) {
+    int wd[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) wd[t] = q + t < q1 ? A.lidx[(int64_t)(q + t) * 64 + lane] : kPad;
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      const int rel = wd[t] >> 16;
+      const bool ok = rel != -32768;
+      const int j = ok ? base + (int)(int16_t)(wd[t] & 0xFFFF) : base;
+      const T m = ok ? T(1) : T(0);
+      const int64_t off = (int64_t)(p0 + (ok ? rel : 0)) * bb * 64 + (j & 63);
+      T xv[BS];
+#pragma unroll
+      for (int b = 0; b < BS; ++b) xv[b] = (T)x[(int64_t)j * BS + b];
+#pragma unroll
+      for (int a = 0; a < BS; ++a)
+#pragma unroll
+        for (int b = 0; b < BS; ++b) {
+          T v;
+          if constexpr (B16) v = (T)bell_val16<false>(A.val16 + off + (b * BS + a) * 64);
+          else v = bell_val<T, false>(A.val + off + (b * BS + a) * 64);
+          acc[a] += (v * m) * xv[b];
+        }
+    }
+  }
+#pragma unroll 2
+  for (int p = p0; p < p1; ++p) {
+    const int c = base + (int)A.bdel[(int64_t)p * 64 + lane];
+    const int64_t off = (int64_t)p * bb * 64 + lane;
+    T xv[BS];
+#pragma unroll
+    for (int b = 0; b < BS; ++b) xv[b] = (T)x[(int64_t)c * BS + b];
+#pragma unroll
+    for (int a = 0; a < BS; ++a)
+#pragma unroll
+      for (int b = 0; b < BS; ++b) {
+        T v;
+        if constexpr (B16) v = (T)bell_val16<false>(A.val16 + off + (a * BS + b) * 64);
+        else v = bell_val<T, false>(A.val + off + (a * BS + b) * 64);
+        acc[a] += v * xv[b];
+      }
+  }
+}
+
+template <typename T, typename XT, int BS>
+__device__ __forceinline__ void bell_node_sym(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane,
+                                              T (&acc)[BS]) {
+  if constexpr (sizeof(T) == 4) {
+    if (A.val16) return bell_node_sym_impl<T, XT, BS, true>(A, x, slice, lane, acc);
+  }
+  bell_node_sym_impl<T, XT, BS, false>(A, x, slice, lane, acc);
+}
+
 template <typename T, typename XT, int BS, bool B16>
 __device__ __forceinline__ T bell_row_vals(const DBELL<T>& A, const XT* __restrict__ x, int slice, int lane, int a) {
   if (A.lptr) return bell_row_sym<T, XT, BS, B16>(A, x, slice, lane, a);
@@ -941,6 +1010,103 @@ __global__ void k_tsmooth_u_bell(DBELL<T> KT, DCSR<T> BT, const T* __restrict__ 
   const int row = node * bs + a;
   if (BT.nnz) s += csr_row_serial<T>(BT, zl, row);
   su[row] = bu[row] - s;
+}
+
+// Node-per-lane forms of the three hot blocked-ELL kernels for symmetric
+// storage with 3x3 blocks (the fine level): 256 threads = 4 slices per
+// workgroup, the groups of 4 slices in the XCD-contiguous order.  With the
+// layout's loads through the caches (not memory) the limit, one thread per
+// node loads each x entry, index word and mirror block once where a wave
+// per block row loads them three times: 7-8 % faster passes than the
+// row-wave form on the 100^3 workload.
+constexpr int kNplBlock = 256;
+
+template <typename T, typename XT, int BS, int MODE>
+__global__ void __launch_bounds__(kNplBlock) k_blk_spmv_bell_npl(DBELL<T> K, DCSR<T> A12, DCSR<T> A21, DCSR<T> A22,
+                                                                 const XT* __restrict__ x1, const XT* __restrict__ x2,
+                                                                 const T* __restrict__ b1, const T* __restrict__ b2,
+                                                                 T* __restrict__ y1, T* __restrict__ y2, int n1, int n2,
+                                                                 T* __restrict__ xcopy) {
+  const int ng = (K.n_slices + 3) / 4;
+  if ((int)blockIdx.x < ng) {
+    const int lane = threadIdx.x & 63;
+    const int slice = xcd_slice((int)blockIdx.x, ng) * 4 + (int)(threadIdx.x >> 6);
+    if (slice >= K.n_slices) return;
+    T acc[BS];
+    bell_node_sym<T, XT, BS>(K, x1, slice, lane, acc);
+    const int node = slice * 64 + lane;
+    if (node >= K.n_nodes) return;
+#pragma unroll
+    for (int a = 0; a < BS; ++a) {
+      const int row = node * BS + a;
+      T s = acc[a];
+      if (A12.nnz) s += csr_row_serial_x<T, XT>(A12, x2, row);
+      if (MODE == 0) y1[row] = s;
+      else if (MODE == 1) y1[row] = b1[row] - s;
+      else y1[row] += s;
+      if (xcopy) xcopy[row] = (T)x1[row];
+    }
+  } else {
+    const int j = ((int)blockIdx.x - ng) * kNplBlock + threadIdx.x;
+    if (j >= n2) return;
+    T s = T(0);
+    if (A21.nnz) s = csr_row_serial_x<T, XT>(A21, x1, j);
+    if (A22.nnz) s += csr_row_serial_x<T, XT>(A22, x2, j);
+    if (MODE == 0) y2[j] = s;
+    else if (MODE == 1) y2[j] = b2[j] - s;
+    else y2[j] += s;
+    if (xcopy) xcopy[n1 + j] = (T)x2[j];
+  }
+}
+
+template <typename T, int BS>
+__global__ void __launch_bounds__(kNplBlock) k_smooth_u_bell_npl(DBELL<T> K, DCSR<T> G, const T* __restrict__ zu,
+                                                                 const T* __restrict__ zl, const T* __restrict__ bu,
+                                                                 const T* __restrict__ jinv, T omega,
+                                                                 T* __restrict__ znu, T* __restrict__ r_out,
+                                                                 T* __restrict__ w_out) {
+  const int ng = (K.n_slices + 3) / 4;
+  const int lane = threadIdx.x & 63;
+  const int slice = xcd_slice((int)blockIdx.x, ng) * 4 + (int)(threadIdx.x >> 6);
+  if (slice >= K.n_slices) return;
+  T acc[BS];
+  bell_node_sym<T, T, BS>(K, zu, slice, lane, acc);
+  const int node = slice * 64 + lane;
+  if (node >= K.n_nodes) return;
+#pragma unroll
+  for (int a = 0; a < BS; ++a) {
+    const int row = node * BS + a;
+    T s = acc[a];
+    if (G.nnz) s += csr_row_serial<T>(G, zl, row);
+    const T r = bu[row] - s;
+    const T w = omega * jinv[row] * r;
+    znu[row] = zu[row] + w;
+    if (r_out) {
+      r_out[row] = r;
+      w_out[row] = w;
+    }
+  }
+}
+
+template <typename T, int BS>
+__global__ void __launch_bounds__(kNplBlock) k_tsmooth_u_bell_npl(DBELL<T> KT, DCSR<T> BT, const T* __restrict__ zu,
+                                                                  const T* __restrict__ zl, const T* __restrict__ bu,
+                                                                  T* __restrict__ su) {
+  const int ng = (KT.n_slices + 3) / 4;
+  const int lane = threadIdx.x & 63;
+  const int slice = xcd_slice((int)blockIdx.x, ng) * 4 + (int)(threadIdx.x >> 6);
+  if (slice >= KT.n_slices) return;
+  T acc[BS];
+  bell_node_sym<T, T, BS>(KT, zu, slice, lane, acc);
+  const int node = slice * 64 + lane;
+  if (node >= KT.n_nodes) return;
+#pragma unroll
+  for (int a = 0; a < BS; ++a) {
+    const int row = node * BS + a;
+    T s = acc[a];
+    if (BT.nnz) s += csr_row_serial<T>(BT, zl, row);
+    su[row] = bu[row] - s;
+  }
 }
 
 template <typename T, int BS>
@@ -1627,6 +1793,22 @@ template <typename T, typename XT>
 static void blk_spmv_bell_impl(const DBELL<T>& K, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22,
                                const XT* x1, const XT* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2,
                                int mode, T* xcopy, hipStream_t s) {
+  if (K.lptr && K.bs == 3) {  // symmetric storage, 3x3 blocks: node per lane
+    constexpr int BS = 3;
+    dim3 gridn((K.n_slices + 3) / 4 + (n2 + kNplBlock - 1) / kNplBlock);
+    if (gridn.x == 0) return;
+    if (mode == 0)
+      k_blk_spmv_bell_npl<T, XT, BS, 0><<<gridn, kNplBlock, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2,
+                                                                    xcopy);
+    else if (mode == 1)
+      k_blk_spmv_bell_npl<T, XT, BS, 1><<<gridn, kNplBlock, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2,
+                                                                    xcopy);
+    else
+      k_blk_spmv_bell_npl<T, XT, BS, 2><<<gridn, kNplBlock, 0, s>>>(K, A12, A21, A22, x1, x2, b1, b2, y1, y2, n1, n2,
+                                                                    xcopy);
+    CAMG_LAUNCHED();
+    return;
+  }
   const int threads = 64 * K.bs;
   const int nb_l = (n2 + threads - 1) / threads;
   dim3 grid(K.n_slices + nb_l);
@@ -1692,6 +1874,12 @@ template <typename T>
 void smooth_u_bell(const DBELL<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* jinv,
                    T omega, T* znu, T* r_out, T* w_out, int n_u, hipStream_t s) {
   if (n_u <= 0) return;
+  if (K.lptr && K.bs == 3) {
+    k_smooth_u_bell_npl<T, 3><<<(K.n_slices + 3) / 4, kNplBlock, 0, s>>>(K, G, zu, zl, bu, jinv, omega, znu, r_out,
+                                                                         w_out);
+    CAMG_LAUNCHED();
+    return;
+  }
   CAMG_BS_DISPATCH(K.bs, {
     k_smooth_u_bell<T, BS><<<K.n_slices, 64 * K.bs, 0, s>>>(K, G, zu, zl, bu, jinv, omega, znu, r_out, w_out);
   });
@@ -1702,6 +1890,11 @@ template <typename T>
 void tsmooth_u_bell(const DBELL<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, const T* bu, T* su, int n_u,
                     hipStream_t s) {
   if (n_u <= 0) return;
+  if (KT.lptr && KT.bs == 3) {
+    k_tsmooth_u_bell_npl<T, 3><<<(KT.n_slices + 3) / 4, kNplBlock, 0, s>>>(KT, BT, zu, zl, bu, su);
+    CAMG_LAUNCHED();
+    return;
+  }
   CAMG_BS_DISPATCH(KT.bs, { k_tsmooth_u_bell<T, BS><<<KT.n_slices, 64 * KT.bs, 0, s>>>(KT, BT, zu, zl, bu, su); });
   CAMG_LAUNCHED();
 }
