@@ -272,7 +272,10 @@ int amg_get_level_matrix(const amg_handle* h, int level, int which, int64_t* nro
  * operator and the FP64 level-0 smoother operator use the new values; the
  * coarse levels, the smoother diagonals, the Schur matrix and an FP32
  * level-0 copy keep the setup-time values (a fixed preconditioner for the
- * new operator). */
+ * new operator).  When K is kept in symmetric blocked-ELL storage, new K
+ * values are checked on the device (the call then waits for hip_stream): if
+ * they are not symmetric, the FP64 kernels use CSR copies of K and K^T until
+ * a later update is symmetric again (amg_level_info.k_sym_stale). */
 int amg_update_fine_values(amg_handle* h, const double* K_val, const double* G_val, const double* B_val,
                            const double* C_val, void* hip_stream);
 
