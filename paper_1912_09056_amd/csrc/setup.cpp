@@ -947,7 +947,10 @@ HostCSR transpose(const HostCSR& A, std::vector<int32_t>* perm) {
 }
 
 void build_hierarchy(std::vector<HostLevel>& levels, const SetupOptions& opt) {
-  levels[0].k_symmetric = csr_equals_transpose(levels[0].K);
+  {
+    PhaseTimer pt("symmetry check");
+    levels[0].k_symmetric = csr_equals_transpose(levels[0].K);
+  }
   while ((int)levels.size() < opt.max_levels && levels.back().n() > opt.max_coarse_rows) {
     HostLevel nxt = coarsen(levels.back(), opt);
     if (nxt.n() >= levels.back().n()) {

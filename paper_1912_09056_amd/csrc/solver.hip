@@ -1667,10 +1667,13 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   const int64_t nu = p->K.nrows, nl = p->C.nrows;
   if (nu <= 0 || nu % p->dim) api_fail(CAMG_ERR_SHAPE, "n_u must be a positive multiple of dim");
   if (nl < 0 || nu + nl >= (int64_t(1) << 31)) api_fail(CAMG_ERR_SHAPE, "system too large");
-  check_csr(p->K, nu, nu, "K");
-  check_csr(p->G, nu, nl, "G");
-  check_csr(p->B, nl, nu, "B");
-  check_csr(p->C, nl, nl, "C");
+  {
+    PhaseTimer pt("input checks");
+    check_csr(p->K, nu, nu, "K");
+    check_csr(p->G, nu, nl, "G");
+    check_csr(p->B, nl, nu, "B");
+    check_csr(p->C, nl, nl, "C");
+  }
   if ((p->n_slave > 0 && !p->slave_dofs) || (p->n_master > 0 && !p->master_dofs) || p->n_slave < 0 ||
       p->n_master < 0)
     api_fail(CAMG_ERR_INVALID_ARG, "interface dof lists");
@@ -1682,10 +1685,13 @@ static std::unique_ptr<amg_handle> build_host(const amg_problem* p, const amg_op
   h->n = nu + nl;
 
   HostLevel L0;
-  L0.K = to_host(p->K);
-  L0.G = to_host(p->G);
-  L0.B = to_host(p->B);
-  L0.C = to_host(p->C);
+  {
+    PhaseTimer pt("input copies");
+    L0.K = to_host(p->K);
+    L0.G = to_host(p->G);
+    L0.B = to_host(p->B);
+    L0.C = to_host(p->C);
+  }
   L0.bs_u = p->dim;
   L0.bs_l = p->dim;
   const int64_t nn = nu / p->dim;
