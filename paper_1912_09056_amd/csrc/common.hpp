@@ -117,7 +117,8 @@ struct DCSR {
 template <typename T>
 struct DBELL {
   int32_t n_nodes = 0, bs = 0, n_slices = 0;
-  int32_t stream = 0;  // 1: load the values nontemporally (they are read once per pass)
+  int32_t stream = 0;  // 1: load the values nontemporally (they are read once per pass);
+                       // symmetric storage: 1 selects the node-per-lane kernels
   const int32_t* slice_ptr = nullptr;
   const int32_t* bcol = nullptr;
   const int16_t* bdel = nullptr;

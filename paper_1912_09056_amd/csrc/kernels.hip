@@ -1018,7 +1018,8 @@ __global__ void k_tsmooth_u_bell(DBELL<T> KT, DCSR<T> BT, const T* __restrict__ 
 // layout's loads through the caches (not memory) the limit, one thread per
 // node loads each x entry, index word and mirror block once where a wave
 // per block row loads them three times: 7-8 % faster passes than the
-// row-wave form on the 100^3 workload.
+// row-wave form on the 100^3 workload.  A view selects them with `stream`
+// (set for large levels: a third of the waves must still fill the chip).
 constexpr int kNplBlock = 256;
 
 template <typename T, typename XT, int BS, int MODE>
@@ -1793,7 +1794,7 @@ template <typename T, typename XT>
 static void blk_spmv_bell_impl(const DBELL<T>& K, const DCSR<T>& A12, const DCSR<T>& A21, const DCSR<T>& A22,
                                const XT* x1, const XT* x2, const T* b1, const T* b2, T* y1, T* y2, int n1, int n2,
                                int mode, T* xcopy, hipStream_t s) {
-  if (K.lptr && K.bs == 3) {  // symmetric storage, 3x3 blocks: node per lane
+  if (K.lptr && K.stream && K.bs == 3) {  // symmetric storage, 3x3 blocks: node per lane
     constexpr int BS = 3;
     dim3 gridn((K.n_slices + 3) / 4 + (n2 + kNplBlock - 1) / kNplBlock);
     if (gridn.x == 0) return;
@@ -1874,7 +1875,7 @@ template <typename T>
 void smooth_u_bell(const DBELL<T>& K, const DCSR<T>& G, const T* zu, const T* zl, const T* bu, const T* jinv,
                    T omega, T* znu, T* r_out, T* w_out, int n_u, hipStream_t s) {
   if (n_u <= 0) return;
-  if (K.lptr && K.bs == 3) {
+  if (K.lptr && K.stream && K.bs == 3) {
     k_smooth_u_bell_npl<T, 3><<<(K.n_slices + 3) / 4, kNplBlock, 0, s>>>(K, G, zu, zl, bu, jinv, omega, znu, r_out,
                                                                          w_out);
     CAMG_LAUNCHED();
@@ -1890,7 +1891,7 @@ template <typename T>
 void tsmooth_u_bell(const DBELL<T>& KT, const DCSR<T>& BT, const T* zu, const T* zl, const T* bu, T* su, int n_u,
                     hipStream_t s) {
   if (n_u <= 0) return;
-  if (KT.lptr && KT.bs == 3) {
+  if (KT.lptr && KT.stream && KT.bs == 3) {
     k_tsmooth_u_bell_npl<T, 3><<<(KT.n_slices + 3) / 4, kNplBlock, 0, s>>>(KT, BT, zu, zl, bu, su);
     CAMG_LAUNCHED();
     return;

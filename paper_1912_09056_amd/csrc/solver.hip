@@ -382,6 +382,7 @@ struct DevBell {
   DBuf<float> v32;
   DBuf<uint16_t> v16;  // bfloat16 words in place of v32 (fine-level K with CAMG_PREC_MIXED_BF16)
   DBuf<int32_t> lptr, lidx;  // symmetric storage: lower positions
+  bool npl = false;          // symmetric storage: node-per-lane kernels
   template <typename T>
   DBELL<T> view() const {
     DBELL<T> d;
@@ -404,6 +405,7 @@ struct DevBell {
       const size_t bytes = v16.p ? v16.n * sizeof(uint16_t) : v32.n * sizeof(float);
       d.stream = bytes > (size_t(192) << 20) ? 1 : 0;
     }
+    if (lptr.p) d.stream = npl ? 1 : 0;
     return d;
   }
 };
@@ -826,6 +828,10 @@ static void upload_hierarchy(amg_handle& h, hipStream_t s) {
             CAMG_HIP(hipStreamSynchronize(s));
           }
           upload_bell(D.Kb, hb, f64, f32, s, b16);
+          // one wave per slice: only levels with enough slices to fill the
+          // chip (8192: 32 waves on each of the 256 compute units), or any
+          // level when the blocked-ELL layout is forced
+          D.Kb.npl = fmt == CAMG_SPMV_BELL || hb.n_slices >= 8192;
           D.k_lower = hb.n_lower;
           D.k_nnz_stored = hb.nnz_stored;
         } else {
