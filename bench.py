@@ -344,8 +344,9 @@ def main():
         "mixed_vs_fp64_solution_rel_diff": diff,
         "paper_context": PAPER_CONTEXT,
         "roofline": {
-            "kernel": ("level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell: sliced blocked-ELL K, "
-                       "symmetric storage)") if sym else
+            "kernel": ("level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell_npl, one thread per node, on "
+                       "levels of 8192 slices or more, else k_smooth_u_bell: sliced blocked-ELL K, symmetric "
+                       "storage)") if sym else
                       "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u_bell: sliced blocked-ELL K)"
                       if info0["k_layout"] == 1 else "level-0 CheapSIMPLE residual+Jacobi, FP32 (k_smooth_u: CSR K)",
             "bound": "hbm",
