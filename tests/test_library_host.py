@@ -398,3 +398,47 @@ def test_rank_deficient_aggregate_is_reported():
     with pytest.raises(Exception) as e:
         build_hierarchy(pn, OracleOptions(max_levels=2))
     assert "rank" in str(e.value).lower()
+
+
+def _exactly_symmetric(A):
+    At = A.T.tocsr()
+    At.sort_indices()
+    return (np.array_equal(A.indptr, At.indptr) and np.array_equal(A.indices, At.indices)
+            and np.array_equal(A.data, At.data))
+
+
+def _pair2(prob, okw, lkw):
+    from paper_1912_09056_amd.camg import AMGOptions, AMGSolver
+
+    return build_hierarchy(prob, OracleOptions(**okw)), AMGSolver.from_problem(prob, AMGOptions(**lkw),
+                                                                              host_only=True)
+
+
+@pytest.mark.parametrize("okw,lkw", [(dict(max_levels=4), dict(max_levels=4)),
+                                     (dict(max_levels=4, prolongator="sa"), dict(max_levels=4, prolongator=1))])
+def test_coarse_stiffness_symmetric_iff_fine_is(okw, lkw):
+    """A fine K equal to its transpose gives coarse K's equal to theirs bit
+    for bit (each mirrored pair of the Galerkin product replaced by its mean),
+    within the 1e-13 bar of the oracle's unsymmetrised product; a fine K that
+    is not symmetric leaves the Galerkin products as computed."""
+    import dataclasses
+
+    prob = make_workload("contact3d_6", slave_elems=(8, 8, 8), master_elems=(9, 9, 8))
+    ora, lib = _pair2(prob, okw, lkw)
+    assert _exactly_symmetric(prob.K.tocsr())
+    for l in range(lib.n_levels):
+        K = lib.level_matrix(l, "K")
+        assert _exactly_symmetric(K), l
+        R = ora[l].K
+        assert np.abs(K.data - R.data).max() <= 1e-13 * max(1.0, np.abs(R.data).max()), l
+    # one entry off its mirror by one unit in the last place
+    K1 = prob.K.tocsr().copy()
+    rows = np.repeat(np.arange(K1.shape[0]), np.diff(K1.indptr))
+    k = int(np.argmax(np.abs(K1.data) * (rows != K1.indices)))  # the largest off-diagonal entry
+    K1.data[k] = np.nextafter(K1.data[k], np.inf)
+    ora1, lib1 = _pair2(dataclasses.replace(prob, K=K1), okw, lkw)
+    assert not _exactly_symmetric(lib1.level_matrix(0, "K"))
+    for l in range(1, lib1.n_levels):
+        K = lib1.level_matrix(l, "K")
+        R = ora1[l].K
+        assert np.abs(K.data - R.data).max() <= 1e-13 * max(1.0, np.abs(R.data).max()), l
