@@ -371,6 +371,7 @@ def main():
             "nnz_K": prob.K.nnz,
             "full_storage_bytes_per_launch": full_bytes,
             "full_storage_equivalent_GBps": full_bytes / avg_s / 1e9,
+            "full_storage_equivalent_frac": full_bytes / avg_s / 1e9 / peak,
             "k_layout": {1: "sliced blocked-ELL", 3: "sliced blocked-ELL, symmetric storage"}.get(
                 info0["k_layout"], "CSR"),
             "k_blocks": info0["k_blocks"],
