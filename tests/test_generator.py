@@ -331,3 +331,33 @@ def test_stiffness_equals_its_transpose_bit_for_bit(name):
         Kt.sort_indices()
         assert np.array_equal(K.indptr, Kt.indptr) and np.array_equal(K.indices, Kt.indices)
         assert np.array_equal(K.data, Kt.data)
+
+
+@pytest.mark.parametrize("dim,nel", [(2, (4, 3)), (3, (3, 2, 2))])
+def test_body_stiffness_equals_plain_element_sum(dim, nel):
+    """The structured assembly (blockwise, then each mirrored block pair
+    replaced by its mean) equals the element-by-element sum written out with
+    a plain COO scatter, to rounding, and is symmetric bit for bit: a wrong
+    mirror pairing in the symmetrisation would show as an O(1) difference."""
+    K, X = _body(dim, nel, sigma=1.0)
+    axes = _grid_coords(nel, [0.0] * dim, [1.0, 0.8, 0.6][:dim])
+    Kl, Km = _element_shapes(nel, axes, None)
+    rng = np.random.default_rng(1)
+    grid = tuple(reversed(nel))
+    lam, mu = lame_from_E_nu(rng.lognormal(0.0, 1.0, grid), 0.3)
+    nn = [n + 1 for n in nel]
+    offs = np.array([[(l >> k) & 1 for k in range(dim)] for l in range(2 ** dim)])
+    rows, cols, vals = [], [], []
+    for e in np.ndindex(*grid):  # e = (z, y, x) or (y, x)
+        ex = tuple(reversed(e))  # element index along x first
+        nodes = [sum((ex[k] + o[k]) * int(np.prod(nn[:k])) for k in range(dim)) for o in offs]
+        dofs = np.array([n * dim + c for n in nodes for c in range(dim)])
+        Ke = lam[e] * Kl.reshape(Kl.shape[-2:]) + mu[e] * Km.reshape(Km.shape[-2:])
+        rows.append(np.repeat(dofs, dofs.size))
+        cols.append(np.tile(dofs, dofs.size))
+        vals.append(Ke.ravel())
+    n = int(np.prod(nn)) * dim
+    R = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).toarray()
+    D = K.toarray()
+    assert np.abs(D - R).max() <= 1e-14 * np.abs(R).max()
+    assert np.array_equal(D, D.T)
